@@ -1,0 +1,200 @@
+"""Level sets (signed distance, voxel units) and phase labels of simple shapes.
+
+Every function returns ``(L, phase)`` as flat float64 / int32 arrays over the
+nodes, or helpers to build them.  Inclusions get L < 0 and label >= 1; the
+matrix gets L > 0 and label 0.
+"""
+
+import numpy as np
+
+from .grid import node_coords, periodic_delta
+
+
+def spheres_levelset(n, centers, radii):
+    """Signed distance to the nearest of several periodic spheres.
+
+    L(x) = min_i(|x - c_i|_periodic - r_i); the label is 1 + argmin where L < 0.
+    """
+    x, y, z = node_coords(n)
+    best = np.full(x.shape, np.inf)
+    lab = np.zeros(x.shape, dtype=np.int32)
+    for idx, (c, r) in enumerate(zip(centers, radii)):
+        dx = periodic_delta(x, c[0], n[0])
+        dy = periodic_delta(y, c[1], n[1])
+        dz = periodic_delta(z, c[2], n[2])
+        d = np.sqrt(dx * dx + dy * dy + dz * dz) - r
+        better = d < best
+        best = np.where(better, d, best)
+        lab = np.where(better, idx + 1, lab)
+    phase = np.where(best < 0.0, lab, 0).astype(np.int32)
+    return best.astype(np.float64), phase
+
+
+def rsa_spheres(n, count, radius_sampler, gap, rng, max_tries=200000, target_vf=None):
+    """Random sequential addition of non-overlapping periodic spheres.
+
+    Centres are uniform in the cell; a candidate is accepted when its surface
+    keeps at least ``gap`` voxels from every accepted sphere.  Stops after
+    ``count`` spheres, or, when ``target_vf`` is given, once the analytic volume
+    fraction reaches it.
+    """
+    n = np.asarray(n, dtype=np.float64)
+    vol = float(np.prod(n))
+    centers, radii = [], []
+    tries = 0
+    vf = 0.0
+    while True:
+        if target_vf is None and len(centers) >= count:
+            break
+        if target_vf is not None and vf >= target_vf:
+            break
+        if tries >= max_tries:
+            raise RuntimeError("RSA did not place the requested inclusions")
+        tries += 1
+        r = float(radius_sampler(rng))
+        c = rng.uniform(0.0, 1.0, 3) * n
+        ok = True
+        for c2, r2 in zip(centers, radii):
+            d = periodic_delta(c, np.asarray(c2), n)
+            if np.sqrt(np.sum(d * d)) < r + r2 + gap:
+                ok = False
+                break
+        if ok:
+            centers.append(c)
+            radii.append(r)
+            vf += 4.0 / 3.0 * np.pi * r ** 3 / vol
+    return np.array(centers), np.array(radii)
+
+
+def laminate_levelset(n, m, s1, s2):
+    """Periodic rank-one laminate with integer normal direction ``m``.
+
+    The phase coordinate s = m . x (mod n0, n0 = n1 = n2 required) places layer
+    1 at s in [s1, s2).  L is the exact signed distance to the nearest plane of
+    the family (negative in layer 1); layer 1 gets label 1.
+    """
+    assert n[0] == n[1] == n[2]
+    N = float(n[0])
+    m = np.asarray(m, dtype=np.float64)
+    norm = np.sqrt(np.sum(m * m))
+    x, y, z = node_coords(n)
+    s = m[0] * x + m[1] * y + m[2] * z
+    w = float(s2 - s1)
+    t = np.mod(s - s1, N)
+    inside = t < w
+    d_in = np.minimum(t, w - t)
+    d_out = np.minimum(t - w, N - t)
+    L = np.where(inside, -d_in, d_out) / norm
+    phase = np.where(inside, 1, 0).astype(np.int32)
+    return L, phase
+
+
+def coated_sphere_levelset(n, center, r_inclusion, r_coating):
+    """Coated sphere: matrix (label 0, L > 0), coating (1, L < 0), core (2, L > 0).
+
+    The level set changes sign at both spherical interfaces and is the signed
+    distance to the nearer one.
+    """
+    x, y, z = node_coords(n)
+    dx = periodic_delta(x, center[0], n[0])
+    dy = periodic_delta(y, center[1], n[1])
+    dz = periodic_delta(z, center[2], n[2])
+    r = np.sqrt(dx * dx + dy * dy + dz * dz)
+    L = np.where(r >= r_coating, r - r_coating,
+                 np.where(r >= r_inclusion, -np.minimum(r_coating - r, r - r_inclusion), r_inclusion - r))
+    phase = np.where(r >= r_coating, 0, np.where(r >= r_inclusion, 1, 2)).astype(np.int32)
+    return L.astype(np.float64), phase
+
+
+def _ellipsoid_distance(p, axes):
+    """Signed distance from points p (m x 3, local frame) to an ellipsoid.
+
+    Closest-point root of F(t) = sum (a_i p_i / (t + a_i^2))^2 - 1 found by
+    bisection on t in (-min a^2, inf) (Eberly's formulation); negative inside.
+    """
+    a = np.asarray(axes, dtype=np.float64)
+    q = np.abs(p)
+    a2 = a * a
+    inside = np.sum((q / a) ** 2, axis=1) < 1.0
+    lo = np.where(inside, -a2.min() * (1.0 - 1e-15), 0.0)
+    hi = np.where(inside, 0.0, np.sqrt(np.sum(q * q, axis=1)) * a.max() + a2.max())
+    for _ in range(200):
+        t = 0.5 * (lo + hi)
+        F = np.sum((a[None, :] * q / (t[:, None] + a2[None, :])) ** 2, axis=1) - 1.0
+        pos = F > 0.0
+        lo = np.where(pos, t, lo)
+        hi = np.where(pos, hi, t)
+    t = 0.5 * (lo + hi)
+    xc = a2[None, :] * q / (t[:, None] + a2[None, :])
+    d = np.sqrt(np.sum((xc - q) ** 2, axis=1))
+    return np.where(inside, -d, d)
+
+
+def ellipsoids_levelset(n, centers, axes, rotations, clamp=3.0):
+    """Signed distance (clamped to +-clamp) to the nearest of several ellipsoids.
+
+    ``rotations[i]`` maps local to global coordinates.  Nodes farther than
+    ``clamp`` from every surface get L = +clamp (matrix) or -clamp (inside).
+    """
+    x, y, z = node_coords(n)
+    L = np.full(x.shape, clamp)
+    phase = np.zeros(x.shape, dtype=np.int32)
+    for idx, (c, ax, R) in enumerate(zip(centers, axes, rotations)):
+        reach = float(np.max(ax)) + clamp + 1.0
+        dx = periodic_delta(x, c[0], n[0])
+        dy = periodic_delta(y, c[1], n[1])
+        dz = periodic_delta(z, c[2], n[2])
+        near = (np.abs(dx) <= reach) & (np.abs(dy) <= reach) & (np.abs(dz) <= reach)
+        ids = np.nonzero(near)[0]
+        g = np.stack([dx[ids], dy[ids], dz[ids]], axis=1)
+        loc = g @ np.asarray(R)  # row-vector form of R^T g
+        d = np.clip(_ellipsoid_distance(loc, ax), -clamp, clamp)
+        better = d < L[ids]
+        L[ids] = np.where(better, d, L[ids])
+        phase[ids] = np.where(better & (d < 0.0), idx + 1, np.where(better, 0, phase[ids]))
+    return L.astype(np.float64), phase.astype(np.int32)
+
+
+def _random_rotation(rng):
+    """Uniformly distributed rotation matrix (from a random unit quaternion)."""
+    q = rng.normal(size=4)
+    q /= np.linalg.norm(q)
+    w, a, b, c = q
+    return np.array([
+        [1 - 2 * (b * b + c * c), 2 * (a * b - c * w), 2 * (a * c + b * w)],
+        [2 * (a * b + c * w), 1 - 2 * (a * a + c * c), 2 * (b * c - a * w)],
+        [2 * (a * c - b * w), 2 * (b * c + a * w), 1 - 2 * (a * a + b * b)],
+    ])
+
+
+def rsa_ellipsoids(n, count, axes, gap, rng, max_tries=20000):
+    """Random sequential addition of randomly oriented, equal ellipsoids.
+
+    Overlap is tested on the node raster: every candidate's ellipsoid inflated
+    by ``gap / 2`` must not cover a node already covered by an accepted one.
+    """
+    x, y, z = node_coords(n)
+    occupied = np.zeros(x.shape, dtype=bool)
+    ax_inf = np.asarray(axes, dtype=np.float64) + 0.5 * gap
+    reach = float(np.max(ax_inf)) + 1.0
+    centers, rots = [], []
+    tries = 0
+    while len(centers) < count:
+        if tries >= max_tries:
+            raise RuntimeError("ellipsoid RSA did not place the requested inclusions")
+        tries += 1
+        c = rng.uniform(0.0, 1.0, 3) * np.asarray(n, dtype=np.float64)
+        R = _random_rotation(rng)
+        dx = periodic_delta(x, c[0], n[0])
+        dy = periodic_delta(y, c[1], n[1])
+        dz = periodic_delta(z, c[2], n[2])
+        near = (np.abs(dx) <= reach) & (np.abs(dy) <= reach) & (np.abs(dz) <= reach)
+        ids = np.nonzero(near)[0]
+        loc = np.stack([dx[ids], dy[ids], dz[ids]], axis=1) @ R
+        cover = np.sum((loc / ax_inf[None, :]) ** 2, axis=1) <= 1.0
+        if np.any(occupied[ids[cover]]):
+            continue
+        occupied[ids[cover]] = True
+        centers.append(c)
+        rots.append(R)
+    return np.array(centers), np.array(rots)

@@ -1,0 +1,315 @@
+"""X-FEM discretisation of the periodic cell problem (Sec. 2 and Sec. 3).
+
+Everything is in voxel units (h = 1, voxel volume 1).  Physical units enter only
+through the level set, which is divided by h.
+
+Steps, in the paper's order:
+
+1. Nodal level set L^i, linearly interpolated per P1 element (eq. levelset).
+   Values with |L| below 1e-6 are set to zero (Sec. 3: a node closer than that
+   counts as lying on the interface; the threshold is read in voxel units).
+2. A P1 element is *cut* when it has a node with L > 0 and one with L < 0; the
+   enriched node set J is the set of vertices of cut elements (eq. X-FEM space).
+3. Modified abs enrichment rho^m = sum N^i |L^i| - |sum N^i L^i| (eq. modified
+   abs enrichment); enriched shape functions N_X^j = N^j rho (eq. enrichedN).
+4. Cut elements are split along the plane L_h = 0 into subtetrahedra, each
+   integrated by the degree-2 four-point rule (Sec. 3, subdivision).
+5. Scaling factors D0_jj = int ||grad^s N_X^j||^2 (eq. scaling factors), read
+   literally as the squared Frobenius norm of the Voigt-Mandel matrix
+   M (grad N_X^j (x) I_3), summed over the quadrature points.
+6. Element matrices A_e = sum_q w B^T C B, S_e = sum_q w C B (eqs. Kapp_q,
+   Sapp_q) with B = M (grad N (x) I_3) (eq. shapeFunctionGradient).
+
+Material of an element (the paper's two-phase sign convention generalised to
+nodal phase labels): an uncut element takes the label of its vertex with the
+largest |L| (ties: first vertex along the Kuhn path); in a cut element the side
+L > 0 takes the label of its vertex with the largest L and the side L < 0 that
+of its vertex with the largest |L|.
+"""
+
+import numpy as np
+
+from .kuhn import CORNERS, kuhn_tets, bary_gradients, tet_volume
+from .quadrature import degree2_rule, degree3_rule
+
+SQRT2 = np.sqrt(2.0)
+
+
+def mandel(E):
+    """Voigt-Mandel vector of a symmetric 3x3 tensor (11, 22, 33, 23, 13, 12)."""
+    return np.array([E[0, 0], E[1, 1], E[2, 2], SQRT2 * E[1, 2], SQRT2 * E[0, 2], SQRT2 * E[0, 1]])
+
+
+def _mandel_sym_basis():
+    """P[m, c, k] = Mandel component m of sym(e_c (x) e_k)."""
+    P = np.zeros((6, 3, 3))
+    for c in range(3):
+        for k in range(3):
+            H = np.zeros((3, 3))
+            H[c, k] = 1.0
+            P[:, c, k] = mandel(0.5 * (H + H.T))
+    return P
+
+
+_P = _mandel_sym_basis()
+
+
+def mandel_B(g):
+    """6 x 3 matrix mapping a nodal displacement to the Mandel strain of u (x) grad N.
+
+    Column c is Mandel(sym(e_c (x) g)) (eq. shapeFunctionGradient).  ``g`` may
+    carry leading axes (..., 3), giving (..., 6, 3).
+    """
+    return np.einsum("mck,...k->...mc", _P, np.asarray(g, dtype=np.float64))
+
+
+def iso_C(lam, mu):
+    """Isotropic stiffness in Mandel form: lambda 1 (x) 1 + 2 mu I."""
+    one = np.array([1.0, 1.0, 1.0, 0.0, 0.0, 0.0])
+    return lam * np.outer(one, one) + 2.0 * mu * np.eye(6)
+
+
+def subdivide(X, Lv):
+    """Split a cut tetrahedron along the plane where its linear level set vanishes.
+
+    Returns a list of (4 x 3 vertex array, side) with side = +1 for L > 0 and -1
+    for L < 0.  Cases by the number of positive, negative and zero vertices:
+    (1,3,0)/(3,1,0): a corner tetrahedron plus a prism (1 + 3 pieces);
+    (2,2,0): two prisms (6 pieces); (1,2,1)/(2,1,1): a tetrahedron plus a
+    pyramid (1 + 2); (1,1,2): two tetrahedra.
+    """
+    pos = [a for a in range(4) if Lv[a] > 0]
+    neg = [a for a in range(4) if Lv[a] < 0]
+    zer = [a for a in range(4) if Lv[a] == 0]
+
+    def cut(p, q):
+        t = Lv[p] / (Lv[p] - Lv[q])
+        return X[p] + t * (X[q] - X[p])
+
+    out = []
+
+    def prism(a, b, side):
+        # triangles a and b, lateral edges a_i - b_i
+        out.append((np.array([a[0], a[1], a[2], b[0]]), side))
+        out.append((np.array([a[1], a[2], b[0], b[1]]), side))
+        out.append((np.array([a[2], b[0], b[1], b[2]]), side))
+
+    npos, nneg, nzer = len(pos), len(neg), len(zer)
+    if nzer == 0 and {npos, nneg} == {1, 3}:
+        if npos == 1:
+            lone, others, s = pos[0], neg, 1
+        else:
+            lone, others, s = neg[0], pos, -1
+        c = [cut(lone, o) for o in others]
+        out.append((np.array([X[lone], c[0], c[1], c[2]]), s))
+        prism([X[o] for o in others], c, -s)
+    elif nzer == 0 and npos == 2:
+        p1, p2 = pos
+        n1, n2 = neg
+        c11, c12, c21, c22 = cut(p1, n1), cut(p1, n2), cut(p2, n1), cut(p2, n2)
+        prism([X[p1], c11, c12], [X[p2], c21, c22], 1)
+        prism([X[n1], c11, c21], [X[n2], c12, c22], -1)
+    elif nzer == 1:
+        if npos == 1:
+            lone, pair, s = pos[0], neg, 1
+        else:
+            lone, pair, s = neg[0], pos, -1
+        z = zer[0]
+        c1, c2 = cut(lone, pair[0]), cut(lone, pair[1])
+        out.append((np.array([X[lone], X[z], c1, c2]), s))
+        out.append((np.array([X[z], X[pair[0]], X[pair[1]], c2]), -s))
+        out.append((np.array([X[z], X[pair[0]], c2, c1]), -s))
+    elif nzer == 2:
+        p, q = pos[0], neg[0]
+        c = cut(p, q)
+        out.append((np.array([X[p], X[zer[0]], X[zer[1]], c]), 1))
+        out.append((np.array([X[q], X[zer[0]], X[zer[1]], c]), -1))
+    else:
+        raise ValueError("not a cut element")
+    return out
+
+
+def cut_element_qps(X, Lv, pts, wts):
+    """Quadrature data of one cut element: list of (w, grad N_X (4 x 3), side).
+
+    The element (vertices X, nodal level set Lv) is subdivided along L_h = 0;
+    on every piece the rule (barycentric points ``pts``, weights ``wts`` as
+    fractions of the piece volume) is mapped to physical points.  At each point
+    the unscaled enriched gradients grad N_X^a = rho grad N^a + N^a grad rho are
+    evaluated from the definition rho = sum N^i |L^i| - |sum N^i L^i|.
+    """
+    c0, G = bary_gradients(X)
+    out = []
+    for P, side in subdivide(X, Lv):
+        vol = tet_volume(P)
+        for q in range(len(wts)):
+            x = pts[q] @ P
+            Nq = c0 + G @ x
+            Lh = Nq @ Lv
+            rho = Nq @ np.abs(Lv) - abs(Lh)
+            sgn = np.sign(Lh) if Lh != 0.0 else side
+            grad_rho = G.T @ np.abs(Lv) - sgn * (G.T @ Lv)
+            gX = rho * G + np.outer(Nq, grad_rho)        # rows: grad N_X^a
+            out.append((wts[q] * vol, gX, side))
+    return out
+
+
+def d0_contributions(qps):
+    """Per-vertex contribution of one element to D0_jj = int ||M (grad N_X^j (x) I3)||_F^2."""
+    D = np.zeros(4)
+    for (w, gX, _) in qps:
+        Ba = mandel_B(gX)                                # (4, 6, 3)
+        D += w * np.sum(Ba * Ba, axis=(1, 2))
+    return D
+
+
+class Discretization:
+    """Scaled X-FEM discretisation on a periodic voxel grid.
+
+    Parameters
+    ----------
+    n, length : grid nodes per axis and cell edge lengths (cubic voxels).
+    L, phase : flat nodal level set (units of ``length``) and int labels.
+    lame : (nphase, 2) array of (lambda, mu).
+    snap_eps : level-set snapping threshold in voxel units.
+    d0_scale : multiplies every D0_jj (the converged solution does not depend
+        on it; used to check that invariance).
+    rule : "degree2" (the paper's rule) or "degree3" (check of exactness).
+    keep_qp : keep per-quadrature-point B matrices of cut elements (needed for
+        the energy form and its gradient; memory heavy on large grids).
+    """
+
+    def __init__(self, n, length, L, phase, lame, snap_eps=1e-6, d0_scale=1.0, rule="degree2",
+                 keep_qp=True):
+        self.n = tuple(int(v) for v in n)
+        self.N = int(np.prod(self.n))
+        h = float(length[0]) / self.n[0]
+        for k in range(3):
+            if abs(float(length[k]) / self.n[k] - h) > 1e-12 * h:
+                raise ValueError("voxels must be cubic")
+        self.h = h
+        self.lame = np.asarray(lame, dtype=np.float64).reshape(-1, 2)
+        self.phase = np.asarray(phase, dtype=np.int64).ravel()
+        Ls = np.asarray(L, dtype=np.float64).ravel() / h
+        Ls = np.where(np.abs(Ls) < snap_eps, 0.0, Ls)
+        self.Ls = Ls
+        self.volume = float(self.N)          # |Y| in voxel units
+        self.tets = kuhn_tets()
+        self.rule = rule
+
+        # reference tetrahedra: vertex coordinates, barycentric data, volume
+        self.tet_X = [CORNERS[t].astype(np.float64) for t in self.tets]
+        self.tet_bary = [bary_gradients(X) for X in self.tet_X]
+        self.tet_vol = np.array([tet_volume(X) for X in self.tet_X])
+
+        # vertex node indices of every (voxel, tet)
+        n0, n1, n2 = self.n
+        k, j, i = np.meshgrid(np.arange(n2), np.arange(n1), np.arange(n0), indexing="ij")
+        i, j, k = i.ravel(), j.ravel(), k.ravel()
+        self.nvox = self.N
+        vn = np.zeros((self.N, 6, 4), dtype=np.int64)
+        for t, tet in enumerate(self.tets):
+            for a, c in enumerate(tet):
+                off = CORNERS[c]
+                vn[:, t, a] = ((i + off[0]) % n0) + n0 * (((j + off[1]) % n1) + n1 * ((k + off[2]) % n2))
+        self.vert_nodes = vn
+
+        Lv = Ls[vn]
+        self.cut = np.any(Lv > 0, axis=2) & np.any(Lv < 0, axis=2)
+        # uncut material: vertex with the largest |L|, first along the path on ties
+        amax = np.argmax(np.abs(Lv), axis=2)
+        lab_nodes = self.phase[vn]
+        self.tet_label = np.take_along_axis(lab_nodes, amax[..., None], axis=2)[..., 0]
+        if np.any(self.tet_label < 0) or np.any(self.tet_label >= len(self.lame)):
+            raise ValueError("phase label out of range")
+
+        # enriched nodes J: vertices of cut elements, numbered in increasing node order
+        self.J = np.unique(vn[self.cut]) if np.any(self.cut) else np.zeros(0, dtype=np.int64)
+        self.nX = len(self.J)
+        self.jmap = -np.ones(self.N, dtype=np.int64)
+        self.jmap[self.J] = np.arange(self.nX)
+
+        # uncut elements: one B per tet type (FE part only)
+        self.B_fe = []
+        for t in range(6):
+            _, G = self.tet_bary[t]
+            self.B_fe.append(np.concatenate(list(mandel_B(G)), axis=1))
+
+        self.keep_qp = keep_qp
+        self._build_cut_elements(d0_scale)
+
+    # ------------------------------------------------------------------ cut elements
+    def _build_cut_elements(self, d0_scale):
+        pts, wts = degree2_rule() if self.rule == "degree2" else degree3_rule()
+        cv, ct = np.nonzero(self.cut)
+        self.cut_voxel, self.cut_type = cv, ct
+        ncut = len(cv)
+        self.cut_nodes = self.vert_nodes[cv, ct] if ncut else np.zeros((0, 4), dtype=np.int64)
+        raw = []                                  # per cut element: list of qps
+        D0 = np.zeros(self.nX)
+        for e in range(ncut):
+            t = ct[e]
+            Lv = self.Ls[self.cut_nodes[e]]
+            labs = self.phase[self.cut_nodes[e]]
+            # side materials (largest L on + side, largest |L| on - side)
+            lab_pos = labs[int(np.argmax(np.where(Lv > 0, Lv, -np.inf)))]
+            lab_neg = labs[int(np.argmax(np.where(Lv < 0, -Lv, -np.inf)))]
+            qps = cut_element_qps(self.tet_X[t], Lv, pts, wts)
+            D0[self.jmap[self.cut_nodes[e]]] += d0_contributions(qps)
+            raw.append([(w, gX, lab_pos if side > 0 else lab_neg) for (w, gX, side) in qps])
+        self.D0 = D0 * d0_scale
+        if np.any(self.D0 <= 0.0):
+            raise ValueError("non-positive scaling factor")
+        self.D0_isqrt = 1.0 / np.sqrt(self.D0) if self.nX else np.zeros(0)
+
+        # scaled element data
+        self.cut_enr = self.jmap[self.cut_nodes] if ncut else np.zeros((0, 4), dtype=np.int64)
+        self.cut_K = np.zeros((ncut, 24, 24))
+        self.cut_S = np.zeros((ncut, 6, 24))
+        self.cut_Cbar = np.zeros((ncut, 6, 6))
+        self.cut_qp = []                          # (w, B (6 x 24), label) per qp, for gradients
+        for e in range(ncut):
+            t = ct[e]
+            _, G = self.tet_bary[t]
+            scale = self.D0_isqrt[self.cut_enr[e]]
+            B_fe = self.B_fe[t]
+            lst = []
+            for (w, gX, lab) in raw[e]:
+                B = np.zeros((6, 24))
+                B[:, :12] = B_fe
+                B[:, 12:] = np.concatenate(list(mandel_B(scale[:, None] * gX)), axis=1)
+                C = iso_C(*self.lame[lab])
+                self.cut_K[e] += w * B.T @ C @ B
+                self.cut_S[e] += w * C @ B
+                self.cut_Cbar[e] += w * C
+                if self.keep_qp:
+                    lst.append((w, B, lab))
+            self.cut_qp.append(lst)
+
+    # ------------------------------------------------------------------ dof maps
+    @property
+    def ndof(self):
+        return 3 * (self.N + self.nX)
+
+    def element_dofs_uncut(self, t):
+        """(nvox, 12) global dofs of the tet of type t in every voxel (comp-major layout)."""
+        vn = self.vert_nodes[:, t, :]
+        return np.stack([vn[:, a] + c * self.N for a in range(4) for c in range(3)], axis=1)
+
+    def element_dofs_cut(self):
+        """(ncut, 24) global dofs of every cut element: 12 FE then 12 enriched."""
+        ncut = len(self.cut_voxel)
+        d = np.zeros((ncut, 24), dtype=np.int64)
+        for a in range(4):
+            for c in range(3):
+                d[:, 3 * a + c] = self.cut_nodes[:, a] + c * self.N
+                d[:, 12 + 3 * a + c] = 3 * self.N + c * self.nX + self.cut_enr[:, a]
+        return d
+
+    def uncut_lame(self, t):
+        """(nvox, 2) Lame pair of the tet of type t in every voxel (valid where uncut)."""
+        return self.lame[self.tet_label[:, t]]
+
+    def stats(self):
+        return dict(n_enriched=int(self.nX), n_cut_elements=int(len(self.cut_voxel)),
+                    n_cut_voxels=int(len(np.unique(self.cut_voxel))))

@@ -1,0 +1,84 @@
+"""Textbook closed forms used as pins (none of them is the discretisation itself).
+
+* rank-one laminate of isotropic phases (traction continuity + strain
+  compatibility across planar interfaces);
+* composite-sphere bulk modulus (Hashin), the neutral-inclusion construction
+  of the Hashin study;
+* dilute Eshelby estimates for spherical inclusions;
+* Voigt and Reuss bounds.
+"""
+
+import numpy as np
+
+S2 = np.sqrt(2.0)
+
+
+def mandel_to_tensor(v):
+    return np.array([[v[0], v[5] / S2, v[4] / S2],
+                     [v[5] / S2, v[1], v[3] / S2],
+                     [v[4] / S2, v[3] / S2, v[2]]])
+
+
+def tensor_to_mandel(E):
+    return np.array([E[0, 0], E[1, 1], E[2, 2], S2 * E[1, 2], S2 * E[0, 2], S2 * E[0, 1]])
+
+
+def iso_stiffness(lam, mu):
+    one = np.array([1.0, 1.0, 1.0, 0.0, 0.0, 0.0])
+    return lam * np.outer(one, one) + 2.0 * mu * np.eye(6)
+
+
+def laminate_stiffness(normal, fractions, lames):
+    """Effective Mandel stiffness of a rank-one laminate of isotropic phases."""
+    n = np.asarray(normal, dtype=np.float64)
+    n = n / np.linalg.norm(n)
+    C = np.zeros((6, 6))
+    for k in range(6):
+        eb = mandel_to_tensor(np.eye(6)[k])
+        Kinv, rhs = [], []
+        for (lam, mu) in lames:
+            K = mu * np.eye(3) + (lam + mu) * np.outer(n, n)
+            sig = lam * np.trace(eb) * np.eye(3) + 2.0 * mu * eb
+            Kinv.append(np.linalg.inv(K))
+            rhs.append(np.linalg.inv(K) @ (sig @ n))
+        Kavg = sum(f * Ki for f, Ki in zip(fractions, Kinv))
+        t = np.linalg.solve(Kavg, sum(f * r for f, r in zip(fractions, rhs)))
+        savg = np.zeros((3, 3))
+        for f, (lam, mu), Ki in zip(fractions, lames, Kinv):
+            sig0 = lam * np.trace(eb) * np.eye(3) + 2.0 * mu * eb
+            a = Ki @ (t - sig0 @ n)
+            eps = eb + 0.5 * (np.outer(a, n) + np.outer(n, a))
+            savg += f * (lam * np.trace(eps) * np.eye(3) + 2.0 * mu * eps)
+        C[:, k] = tensor_to_mandel(savg)
+    return C
+
+
+def composite_sphere_bulk(Kc, Gc, Ki, f):
+    """Bulk modulus of a composite sphere: core Ki, coating (Kc, Gc), core fraction f."""
+    return Kc + f * (Ki - Kc) / (1.0 + (1.0 - f) * (Ki - Kc) / (Kc + 4.0 * Gc / 3.0))
+
+
+def eshelby_dilute(Km, Gm, Ki, Gi, f):
+    """Dilute-sphere estimates of the effective bulk and shear moduli."""
+    K = Km + f * (Ki - Km) * (3.0 * Km + 4.0 * Gm) / (3.0 * Ki + 4.0 * Gm)
+    zeta = Gm * (9.0 * Km + 8.0 * Gm) / (6.0 * (Km + 2.0 * Gm))
+    G = Gm + f * (Gi - Gm) * (Gm + zeta) / (Gi + zeta)
+    return K, G
+
+
+def voigt_reuss(fractions, lames):
+    """Voigt (arithmetic) and Reuss (harmonic) averages of the phase stiffnesses."""
+    Cs = [iso_stiffness(l, m) for (l, m) in lames]
+    V = sum(f * C for f, C in zip(fractions, Cs))
+    R = np.linalg.inv(sum(f * np.linalg.inv(C) for f, C in zip(fractions, Cs)))
+    return V, R
+
+
+def isotropic_projection(C):
+    """Bulk and shear moduli of the isotropic projection of a Mandel stiffness."""
+    one = np.array([1.0, 1.0, 1.0, 0.0, 0.0, 0.0]) / np.sqrt(3.0)
+    Jp = np.outer(one, one)
+    Kp = np.eye(6) - Jp
+    K = np.trace(Jp @ C) / 3.0
+    G = np.trace(Kp @ C) / 10.0
+    return K, G
