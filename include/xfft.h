@@ -1,0 +1,167 @@
+/*
+ * xfft.h -- C ABI of the MI355X X-FFT solver for periodic 3-D linear-elastic
+ * cell problems (Gehrig & Schneider, arXiv 2601.02172).
+ *
+ * The problem (Sec. 2): find the mean-free periodic displacement fluctuation u
+ * in the scaled X-FEM space (eq. X-FEM scaled space) such that the weak
+ * equilibrium (eq. discreteFormConti) holds for a prescribed macro strain.
+ * Discretisation (Sec. 3): every voxel of a regular grid is split into six P1
+ * tetrahedra; elements cut by the linearly interpolated nodal level set carry
+ * modified-abs enriched shape functions (eqs. enrichedN, modified abs
+ * enrichment) scaled by D0^-1/2 (eq. scaling factors); cut elements are
+ * integrated exactly on the subdivision along the interface.  The system is
+ * solved by the linear CG of Algorithm 1 with the block preconditioner
+ * diag(A11^0, I) (eq. scaledPreconditioner) whose FE block is inverted by FFT
+ * (eq. GreenHermitian), stopped by eq. stoppingCriterion.
+ *
+ * Conventions shared by every entry point:
+ *  - Grid n[3] nodes per axis (periodic; node (i,j,k) at (i,j,k)*h), cubic
+ *    voxels h = len[0]/n[0] = len[1]/n[1] = len[2]/n[2].  Each n[k] must be
+ *    even, >= 4 and of the form 2^a 3^b (FFT radices 2, 3, 4).
+ *  - Nodal arrays have N = n0*n1*n2 entries at index i + n0*(j + n1*k).
+ *  - Symmetric tensors are Voigt-Mandel 6-vectors (11, 22, 33, sqrt2*23,
+ *    sqrt2*13, sqrt2*12); C_eff is the 6x6 Mandel matrix, row-major.
+ *  - Vectors of unknowns (step-level entry points) are component-major: FE
+ *    dof (node i, component c) at c*N + i, followed by the scaled enriched dof
+ *    (enriched node j, component c) at 3N + c*nX + j.  Enriched nodes are
+ *    numbered in increasing node index.  These vectors are in voxel units
+ *    (h = 1); the solve entry points convert displacements to units of len.
+ *  - Host pointers unless the name says _device.  The caller owns every array
+ *    it passes; the library copies inputs during the call and owns all device
+ *    memory of a problem until xfft_destroy.
+ *  - A handle is not thread safe; distinct handles may be used concurrently.
+ *  - Return value: XFFT_OK (0), XFFT_NOT_CONVERGED (+1: outputs hold the last
+ *    iterate), or a negative error code; xfft_strerror names it.
+ */
+#ifndef XFFT_H
+#define XFFT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    XFFT_OK = 0,
+    XFFT_NOT_CONVERGED = 1,
+    XFFT_EINVAL = -1,      /* bad argument: sizes, NaN/Inf, phase out of range, non-PD moduli */
+    XFFT_ENOMEM = -2,      /* device allocation failed */
+    XFFT_EDEVICE = -3,     /* HIP runtime error or no usable gfx950 device */
+    XFFT_EBREAKDOWN = -4   /* CG breakdown: d^T A d <= 0 or not finite */
+};
+
+enum { XFFT_FP64 = 0, XFFT_MIXED = 1, XFFT_FP32 = 2 /* step-level entry points only */ };
+
+typedef struct xfft_problem xfft_problem;
+
+typedef struct {
+    double rtol;        /* tol of eq. stoppingCriterion (default 1e-10) */
+    int32_t maxit;      /* max CG iterations per load; mixed: total inner iterations (default 20000) */
+    int32_t precision;  /* XFFT_FP64 (plain CG in FP64) or XFFT_MIXED (FP32 CG inside FP64
+                           iterative refinement); default XFFT_FP64 */
+    double snap_eps;    /* |L|/h below this is set to 0 (Sec. 3 reads 1e-6; default 1e-6) */
+    double d0_scale;    /* multiplies every D0_jj; the converged result is independent (default 1) */
+    double inner_rtol;  /* mixed: residual reduction of each inner FP32 solve (default 1e-4) */
+    int32_t batch;      /* 1: all loads of a call iterate together; 0: one load at a time (default 1) */
+    int32_t device;     /* HIP device ordinal (default 0) */
+    int32_t check_every;/* host polls convergence every this many iterations (default 8) */
+    void *stream;       /* hipStream_t to run on, or NULL for a library-owned stream */
+} xfft_options;
+
+typedef struct {
+    int32_t *iters;        /* NULL or [nload]: CG iterations (mixed: inner iterations summed) */
+    int32_t *outer_iters;  /* NULL or [nload]: refinement steps (mixed only) */
+    double *final_res;     /* NULL or [nload]: last res / ||<sigma>|| (FP64 criterion) */
+    double seconds_setup;  /* wall time of xfft_setup */
+    double seconds_solve;  /* wall time of the last xfft_solve */
+    int64_t n_enriched;    /* |J| */
+    int64_t n_irregular_voxels; /* voxels with a cut element or mixed element materials */
+    int64_t n_cut_elements;
+    int64_t n_multilabel;  /* cut elements whose vertices on one side carry different labels */
+} xfft_stats;
+
+/* Fill *opt with the defaults listed above. */
+void xfft_default_options(xfft_options *opt);
+
+/* Build a problem (Sec. 2, Sec. 3): snap the level set, find cut elements and
+ * the enriched node set J (eq. X-FEM space), number them, compute the scaling
+ * factors D0 (eq. scaling factors) and the Green-operator tables (eq.
+ * GreenHermitian).  levelset[N] is the nodal signed distance in units of len
+ * (eq. levelset); phase[N] holds nodal labels in [0, nphase); lame[nphase][2]
+ * = (lambda, mu) per phase, each with mu > 0 and 3 lambda + 2 mu > 0 (eq.
+ * boundsStiffness).  Material of an element: uncut -> label of its vertex with
+ * the largest |L|; cut -> side L > 0 takes the label of its vertex with the
+ * largest L, side L < 0 that of its vertex with the largest |L| (ties: first
+ * vertex along the Kuhn path).  On success *out owns device memory until
+ * xfft_destroy.  Errors: EINVAL, ENOMEM, EDEVICE (nothing is allocated then). */
+int xfft_setup(const int32_t n[3], const double len[3], const double *levelset,
+               const int32_t *phase, int32_t nphase, const double *lame,
+               const xfft_options *opt, xfft_problem **out);
+
+/* Solve the cell problem for nload macro strains (Algorithm 1 with eqs.
+ * stoppingCriterion and convergence; mixed precision refines an FP64
+ * residual with FP32 CG corrections).  macro_strain[nload][6].  Outputs, each
+ * optional (NULL):
+ *   disp[nload][3][N]      nodal FE displacement fluctuation in units of len
+ *                          (enriched functions vanish at the nodes);
+ *   stress[nload][6][N]    voxel-average Mandel stress (eq. average stress per voxel);
+ *   avg_stress[nload][6]   cell-average stress <sigma> (eq. average stress);
+ *   c_eff[6][6]            requires nload == 6 with the unit Mandel basis as
+ *                          macro strains (else EINVAL); column k = <sigma> of load k.
+ * stats may be NULL.  Returns OK, NOT_CONVERGED, EBREAKDOWN, EINVAL, ENOMEM, EDEVICE. */
+int xfft_solve(xfft_problem *p, int32_t nload, const double *macro_strain,
+               double *disp, double *stress, double *avg_stress, double *c_eff,
+               xfft_stats *stats);
+
+/* Same as xfft_solve with caller-owned device buffers (e.g. torch tensors):
+ * strain_dev[nload][6], disp_dev[nload][3][N] or NULL, avg_stress_dev[nload][6]
+ * or NULL, all float64 on the problem's device; runs on `stream` (hipStream_t,
+ * NULL = the problem's stream) and returns after it completes. */
+int xfft_solve_device(xfft_problem *p, int32_t nload, const double *strain_dev,
+                      double *disp_dev, double *avg_stress_dev, void *stream,
+                      xfft_stats *stats);
+
+/* Replace the per-phase Lame pairs (same nphase) keeping the geometry, J and
+ * D0 (they do not depend on the moduli).  EINVAL on non-PD moduli. */
+int xfft_set_lame(xfft_problem *p, const double *lame);
+
+/* Gradient of the energy form of C_eff with respect to the Lame pairs, using
+ * the six unit-load solutions of the last xfft_solve (which must have been
+ * called with nload == 6 and the unit Mandel basis): by Galerkin
+ * orthogonality (App. A) dC_kl/dlambda_p = |Y|^-1 int_p tr eps_k tr eps_l and
+ * dC_kl/dmu_p = 2 |Y|^-1 int_p eps_k . eps_l.  dL_dC[6][6] weights the 36
+ * derivatives: grad[p][0] = sum_kl dL_dC[k][l] dC_kl/dlambda_p, grad[p][1]
+ * likewise for mu.  dC_out (NULL or [nphase][2][6][6]) receives the raw
+ * derivatives.  EINVAL if no suitable solve is stored. */
+int xfft_grad_lame(xfft_problem *p, const double *dL_dC, double *grad, double *dC_out);
+
+/* Solve several problems (uneven grids allowed), each for the six unit Mandel
+ * loads, returning c_eff[nprob][6][6]; stats may be NULL or [nprob]. */
+int xfft_batch_solve(xfft_problem *const *ps, int32_t nprob, double *c_eff, xfft_stats *stats);
+
+/* Step-level entry points (host arrays, voxel units, layout above).
+ * xfft_apply_operator: y = r(x) = A x + sum_e Lambda_e^T int B^T C eps_bar
+ *   (eq. resVector with the macro strain; macro_strain NULL means zero, giving
+ *   y = A x); avg_stress (NULL or [6]) = <sigma(eps_bar + grad^s x)>.
+ * xfft_apply_precond: y = P^-1 f (eq. scaledPreconditioner: Green operator of
+ *   eq. GreenHermitian on the FE block, identity on the enriched block);
+ *   res2 (NULL or [1]) = f^T P^-1 f (eq. convergence before the square root).
+ * precision: XFFT_FP64 or XFFT_FP32 (inputs rounded to float, outputs widened). */
+int xfft_apply_operator(xfft_problem *p, int32_t precision, const double *x,
+                        const double *macro_strain, double *y, double *avg_stress);
+int xfft_apply_precond(xfft_problem *p, int32_t precision, const double *f,
+                       double *y, double *res2);
+
+/* Sizes and enriched-node data: info[0..5] = N, nX, irregular voxels, cut
+ * elements, multi-label cut elements, nphase; jlist[nX] (NULL allowed) = node
+ * index of each enriched node; d0[nX] (NULL allowed) = D0_jj. */
+int xfft_get_layout(xfft_problem *p, int64_t *info, int64_t *jlist, double *d0);
+
+void xfft_destroy(xfft_problem *p);
+const char *xfft_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* XFFT_H */

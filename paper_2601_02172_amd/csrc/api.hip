@@ -1,0 +1,684 @@
+// C ABI (include/xfft.h) and the host drivers of the solver: plain FP64 CG
+// (Algorithm 1), FP32 CG inside FP64 iterative refinement, step-level
+// operator / preconditioner applications.
+#include "../../include/xfft.h"
+#include "kernels.h"
+
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+using namespace xfft;
+
+namespace {
+
+#define HIP_OK(x)                                   \
+    do {                                            \
+        if ((x) != hipSuccess) return XFFT_EDEVICE; \
+    } while (0)
+
+double now_s() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+bool size_ok(int n) {
+    if (n < 4 || n > 4096 || (n & 1)) return false;
+    int m = n;
+    while (m % 2 == 0) m /= 2;
+    while (m % 3 == 0) m /= 3;
+    return m == 1;
+}
+
+bool lame_ok(const double *lame, int np) {
+    for (int q = 0; q < np; ++q) {
+        const double l = lame[2 * q], m = lame[2 * q + 1];
+        if (!std::isfinite(l) || !std::isfinite(m) || !(m > 0.0) || !(3.0 * l + 2.0 * m > 0.0)) return false;
+    }
+    return true;
+}
+
+template <typename T> void free_work(Work<T> &w) {
+    T **ptrs[] = {&w.u, &w.f, &w.d, &w.z, &w.ue, &w.fe, &w.de, &w.ze, &w.cutbuf};
+    for (T **q : ptrs) {
+        if (*q) (void)hipFree(*q);
+        *q = nullptr;
+    }
+    if (w.spec) (void)hipFree(w.spec);
+    w.spec = nullptr;
+    w.cap = 0;
+}
+
+template <typename T> int alloc_work(xfft_problem *p, Work<T> &w, int cap) {
+    if (w.cap >= cap) return XFFT_OK;
+    free_work(w);
+    const Geometry &g = p->g;
+    const size_t nf = (size_t)cap * 3 * g.N, ne = (size_t)cap * 3 * (g.nX > 0 ? g.nX : 1);
+    const size_t ns = (size_t)cap * 3 * g.n2 * g.n1 * g.nh;
+    const size_t nc = (size_t)cap * (g.nirr > 0 ? g.nirr : 1) * 48;
+    T **fe_ptrs[] = {&w.u, &w.f, &w.d, &w.z};
+    for (T **q : fe_ptrs)
+        if (hipMalloc(q, nf * sizeof(T)) != hipSuccess) return XFFT_ENOMEM;
+    T **en_ptrs[] = {&w.ue, &w.fe, &w.de, &w.ze};
+    for (T **q : en_ptrs)
+        if (hipMalloc(q, ne * sizeof(T)) != hipSuccess) return XFFT_ENOMEM;
+    if (hipMalloc(&w.spec, ns * sizeof(cpx<T>)) != hipSuccess) return XFFT_ENOMEM;
+    if (hipMalloc(&w.cutbuf, nc * sizeof(T)) != hipSuccess) return XFFT_ENOMEM;
+    w.cap = cap;
+    return XFFT_OK;
+}
+
+int ensure_state(xfft_problem *p, int cap) {
+    if (p->scal_cap >= cap) return XFFT_OK;
+    if (p->partial) (void)hipFree(p->partial);
+    if (p->scal) (void)hipFree(p->scal);
+    if (p->flags) (void)hipFree(p->flags);
+    if (p->ebar) (void)hipFree(p->ebar);
+    if (p->host_flags) (void)hipHostFree(p->host_flags);
+    p->partial = nullptr; p->scal = nullptr; p->flags = nullptr; p->ebar = nullptr; p->host_flags = nullptr;
+    if (hipMalloc(&p->partial, sizeof(double) * NPART * (size_t)p->nslots * cap) != hipSuccess ||
+        hipMalloc(&p->scal, sizeof(Scalars) * cap) != hipSuccess ||
+        hipMalloc(&p->flags, sizeof(Flags) * cap) != hipSuccess ||
+        hipMalloc(&p->ebar, sizeof(double) * 6 * cap) != hipSuccess ||
+        hipHostMalloc(&p->host_flags, sizeof(Flags) * cap, hipHostMallocDefault) != hipSuccess)
+        return XFFT_ENOMEM;
+    p->scal_cap = cap;
+    return XFFT_OK;
+}
+
+// Upload per-rhs macro strains and reset scalars / flags.
+int reset_state(xfft_problem *p, int nrhs, const double *ebar_host) {
+    std::vector<Scalars> sc(nrhs);
+    for (int r = 0; r < nrhs; ++r) {
+        std::memset(&sc[r], 0, sizeof(Scalars));
+        sc[r].tol = p->rtol;
+        sc[r].tol_inner = p->inner_rtol;
+    }
+    HIP_OK(hipMemcpyAsync(p->scal, sc.data(), sizeof(Scalars) * nrhs, hipMemcpyHostToDevice, p->stream));
+    HIP_OK(hipMemsetAsync(p->flags, 0, sizeof(Flags) * nrhs, p->stream));
+    if (ebar_host) HIP_OK(hipMemcpyAsync(p->ebar, ebar_host, sizeof(double) * 6 * nrhs, hipMemcpyHostToDevice, p->stream));
+    return XFFT_OK;
+}
+
+int read_flags(xfft_problem *p, int nrhs, std::vector<Flags> &out) {
+    HIP_OK(hipMemcpyAsync(p->host_flags, p->flags, sizeof(Flags) * nrhs, hipMemcpyDeviceToHost, p->stream));
+    HIP_OK(hipStreamSynchronize(p->stream));
+    out.assign(reinterpret_cast<Flags *>(p->host_flags), reinterpret_cast<Flags *>(p->host_flags) + nrhs);
+    return XFFT_OK;
+}
+
+// One CG iteration of Algorithm 1 on the work fields of precision T.
+template <typename T>
+void cg_iteration(xfft_problem *p, Work<T> &w, const Tables<T> &tb, int nrhs, int parity, int crit) {
+    hipStream_t s = p->stream;
+    launch_operator<T>(p, w, tb, w.d, w.de, w.z, w.ze, false, (T)1, nrhs, p->flags, parity, nullptr, s);
+    launch_scalars(p, SC_ALPHA, crit, nrhs, parity, nullptr, s);
+    launch_green_forward<T>(p, w, tb, w.f, w.z, nrhs, p->flags, parity, s);
+    launch_enr_update<T>(p, w, 1, nullptr, nrhs, p->flags, parity, s);
+    launch_scalars(p, SC_BETA, crit, nrhs, parity, nullptr, s);
+    launch_green_inverse<T>(p, w, tb, 1, nullptr, nrhs, p->flags, parity, s);
+    launch_enr_final<T>(p, w, 1, nrhs, p->flags, parity, s);
+}
+
+// Initial preconditioned residual: d = P^-1 f, res2, convergence flags.
+template <typename T>
+void cg_start(xfft_problem *p, Work<T> &w, const Tables<T> &tb, int nrhs, int crit) {
+    hipStream_t s = p->stream;
+    launch_green_forward<T>(p, w, tb, w.f, nullptr, nrhs, nullptr, 0, s);
+    launch_enr_update<T>(p, w, 0, nullptr, nrhs, nullptr, 0, s);
+    launch_green_inverse<T>(p, w, tb, 2, nullptr, nrhs, nullptr, 0, s);
+    launch_enr_final<T>(p, w, 2, nrhs, nullptr, 0, s);
+    launch_scalars(p, SC_INIT_RES, crit, nrhs, 0, nullptr, s);
+}
+
+// Iterate until no right-hand side is active; returns iterations run.
+template <typename T>
+int cg_loop(xfft_problem *p, Work<T> &w, const Tables<T> &tb, int nrhs, int crit, int *rc) {
+    std::vector<Flags> fl;
+    *rc = read_flags(p, nrhs, fl);
+    if (*rc) return 0;
+    bool any = false;
+    for (int r = 0; r < nrhs; ++r) any |= fl[r].active[0] != 0;
+    int it = 0;
+    const int every = p->check_every > 0 ? p->check_every : 8;
+    while (any && it < p->maxit) {
+        cg_iteration<T>(p, w, tb, nrhs, it & 1, crit);
+        ++it;
+        if (it % every == 0 || it >= p->maxit) {
+            *rc = read_flags(p, nrhs, fl);
+            if (*rc) return it;
+            any = false;
+            for (int r = 0; r < nrhs; ++r) any |= fl[r].active[it & 1] != 0;
+        }
+    }
+    return it;
+}
+
+// Average stress (Mandel) of the FP64 iterate in w64.u for every rhs; optional voxel stress.
+int final_outputs(xfft_problem *p, int nrhs, double *avg_host, double *vstress_dev) {
+    hipStream_t s = p->stream;
+    Work<double> &w = p->w64;
+    launch_operator<double>(p, w, p->t64, w.u, w.ue, w.z, w.ze, true, 1.0, nrhs, nullptr, 0, vstress_dev, s);
+    double *sum_dev = nullptr;
+    HIP_OK(hipMalloc(&sum_dev, sizeof(double) * 7 * nrhs));
+    launch_scalars(p, SC_SUM_ONLY, 0, nrhs, 0, sum_dev, s);
+    std::vector<double> sum(7 * nrhs);
+    hipError_t e1 = hipMemcpyAsync(sum.data(), sum_dev, sizeof(double) * 7 * nrhs, hipMemcpyDeviceToHost, s);
+    hipError_t e2 = hipStreamSynchronize(s);
+    (void)hipFree(sum_dev);
+    if (e1 != hipSuccess || e2 != hipSuccess) return XFFT_EDEVICE;
+    const double V = (double)p->g.N, r2 = std::sqrt(2.0);
+    for (int r = 0; r < nrhs; ++r) {
+        const double *v = &sum[7 * r];
+        double *o = avg_host + 6 * r;
+        o[0] = v[1] / V; o[1] = v[2] / V; o[2] = v[3] / V;
+        o[3] = r2 * v[4] / V; o[4] = r2 * v[5] / V; o[5] = r2 * v[6] / V;
+    }
+    return XFFT_OK;
+}
+
+// Solve nrhs loads whose macro strains are in ebar_host; solution left in w64.u/ue.
+int solve_block(xfft_problem *p, int nrhs, const double *ebar_host, std::vector<int> &iters,
+                std::vector<int> &outer, std::vector<double> &res_rel, int *status) {
+    int rc = alloc_work<double>(p, p->w64, nrhs);
+    if (rc) return rc;
+    if (p->precision == XFFT_MIXED) {
+        rc = alloc_work<float>(p, p->w32, nrhs);
+        if (rc) return rc;
+    }
+    rc = ensure_state(p, nrhs);
+    if (rc) return rc;
+    rc = reset_state(p, nrhs, ebar_host);
+    if (rc) return rc;
+    hipStream_t s = p->stream;
+    Work<double> &w = p->w64;
+    const size_t nf = sizeof(double) * 3 * p->g.N * nrhs, ne = sizeof(double) * 3 * p->g.nX * nrhs;
+    HIP_OK(hipMemsetAsync(w.u, 0, nf, s));
+    if (ne) HIP_OK(hipMemsetAsync(w.ue, 0, ne, s));
+    iters.assign(nrhs, 0);
+    outer.assign(nrhs, 0);
+    res_rel.assign(nrhs, 0.0);
+    std::vector<Flags> fl;
+    *status = XFFT_OK;
+    if (p->precision != XFFT_MIXED) {
+        // f = b = -r(0)
+        launch_operator<double>(p, w, p->t64, nullptr, nullptr, w.f, w.fe, true, -1.0, nrhs, nullptr, 0, nullptr, s);
+        launch_scalars(p, SC_INIT_SIGMA, 0, nrhs, 0, nullptr, s);
+        cg_start<double>(p, w, p->t64, nrhs, 0);
+        cg_loop<double>(p, w, p->t64, nrhs, 0, &rc);
+        if (rc) return rc;
+        rc = read_flags(p, nrhs, fl);
+        if (rc) return rc;
+        for (int r = 0; r < nrhs; ++r) {
+            iters[r] = fl[r].iters;
+            if (fl[r].breakdown) *status = XFFT_EBREAKDOWN;
+            else if (!fl[r].conv && *status == XFFT_OK) *status = XFFT_NOT_CONVERGED;
+        }
+    } else {
+        Work<float> &w32 = p->w32;
+        const int max_outer = 60;
+        bool all_done = false;
+        for (int o = 0; o < max_outer && !all_done; ++o) {
+            // r = b - A u in FP64 (also gives the exact <sigma(u)>)
+            launch_operator<double>(p, w, p->t64, o == 0 ? nullptr : w.u, w.ue, w.f, w.fe, true, -1.0, nrhs, nullptr,
+                                    0, nullptr, s);
+            launch_scalars(p, SC_INIT_SIGMA, 0, nrhs, 0, nullptr, s);
+            launch_round_to_float(p, nrhs, s);
+            cg_start<float>(p, w32, p->t32, nrhs, 0);     // outer criterion on the FP64 residual
+            rc = read_flags(p, nrhs, fl);
+            if (rc) return rc;
+            all_done = true;
+            for (int r = 0; r < nrhs; ++r) {
+                if (!fl[r].pad[0]) { all_done = false; outer[r] = o + 1; }
+            }
+            if (all_done) break;
+            cg_loop<float>(p, w32, p->t32, nrhs, 1, &rc);
+            if (rc) return rc;
+            launch_accumulate_correction(p, nrhs, s);
+            rc = read_flags(p, nrhs, fl);
+            if (rc) return rc;
+            bool stalled = true;
+            for (int r = 0; r < nrhs; ++r) {
+                if (fl[r].breakdown) *status = XFFT_EBREAKDOWN;
+                if (!fl[r].pad[0] && fl[r].iters < p->maxit) stalled = false;
+            }
+            if (stalled || *status == XFFT_EBREAKDOWN) break;
+        }
+        rc = read_flags(p, nrhs, fl);
+        if (rc) return rc;
+        for (int r = 0; r < nrhs; ++r) {
+            iters[r] = fl[r].iters;
+            if (!fl[r].pad[0] && *status == XFFT_OK) *status = XFFT_NOT_CONVERGED;
+        }
+    }
+    // relative final residual of the criterion
+    std::vector<Scalars> sc(nrhs);
+    HIP_OK(hipMemcpyAsync(sc.data(), p->scal, sizeof(Scalars) * nrhs, hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    for (int r = 0; r < nrhs; ++r) {
+        double sn = 0.0;
+        for (int q = 0; q < 6; ++q) sn += sc[r].sigma[q] * sc[r].sigma[q];
+        const double res = std::sqrt(std::fmax(sc[r].res2, 0.0) / (double)p->g.N);
+        res_rel[r] = sn > 0.0 ? res / std::sqrt(sn) : res;
+    }
+    return XFFT_OK;
+}
+
+bool is_unit_basis(int nload, const double *E) {
+    if (nload != 6) return false;
+    for (int k = 0; k < 6; ++k)
+        for (int q = 0; q < 6; ++q)
+            if (E[6 * k + q] != (k == q ? 1.0 : 0.0)) return false;
+    return true;
+}
+
+int solve_impl(xfft_problem *p, int nload, const double *strain, double *disp, double *stress, double *avg_stress,
+               double *c_eff, xfft_stats *stats, bool device_out) {
+    if (!p || nload < 1 || !strain) return XFFT_EINVAL;
+    for (int q = 0; q < 6 * nload; ++q)
+        if (!std::isfinite(strain[q])) return XFFT_EINVAL;
+    const bool unit = is_unit_basis(nload, strain);
+    if (c_eff && !unit) return XFFT_EINVAL;
+    HIP_OK(hipSetDevice(p->device));
+    const double t0 = now_s();
+    const int blk = p->batch ? nload : 1;
+    const int64_t N = p->g.N, nX = p->g.nX;
+    std::vector<double> avg(6 * nload);
+    int status = XFFT_OK;
+    // keep the FP64 solutions for gradients when the unit basis is solved
+    if (unit) {
+        if (!p->sol_u) {
+            if (hipMalloc(&p->sol_u, sizeof(double) * 6 * 3 * N) != hipSuccess) return XFFT_ENOMEM;
+            if (hipMalloc(&p->sol_ue, sizeof(double) * 6 * 3 * (nX > 0 ? nX : 1)) != hipSuccess) return XFFT_ENOMEM;
+        }
+    }
+    p->sol_unit_basis = false;
+    double *vstress_dev = nullptr;
+    for (int l0 = 0; l0 < nload; l0 += blk) {
+        const int nr = (l0 + blk <= nload) ? blk : nload - l0;
+        std::vector<int> it, outer;
+        std::vector<double> res;
+        int st = XFFT_OK;
+        int rc = solve_block(p, nr, strain + 6 * l0, it, outer, res, &st);
+        if (rc) return rc;
+        if (st == XFFT_EBREAKDOWN || (st == XFFT_NOT_CONVERGED && status == XFFT_OK)) status = st;
+        if (stress) {
+            if (device_out) vstress_dev = stress + (size_t)6 * N * l0;
+            else if (!vstress_dev && hipMalloc(&vstress_dev, sizeof(double) * 6 * N * blk) != hipSuccess)
+                return XFFT_ENOMEM;
+        }
+        rc = final_outputs(p, nr, avg.data() + 6 * l0, stress ? vstress_dev : nullptr);
+        if (rc) return rc;
+        hipStream_t s = p->stream;
+        const hipMemcpyKind k_out = device_out ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+        if (disp) {
+            // FE displacement in units of len: voxel units times h
+            std::vector<double> tmp;
+            HIP_OK(hipStreamSynchronize(s));
+            if (device_out) {
+                HIP_OK(hipMemcpyAsync(disp + (size_t)3 * N * l0, p->w64.u, sizeof(double) * 3 * N * nr, k_out, s));
+            } else {
+                HIP_OK(hipMemcpyAsync(disp + (size_t)3 * N * l0, p->w64.u, sizeof(double) * 3 * N * nr, k_out, s));
+                HIP_OK(hipStreamSynchronize(s));
+                for (size_t q = 0; q < (size_t)3 * N * nr; ++q) disp[(size_t)3 * N * l0 + q] *= p->h;
+            }
+        }
+        if (stress && !device_out) {
+            HIP_OK(hipMemcpyAsync(stress + (size_t)6 * N * l0, vstress_dev, sizeof(double) * 6 * N * nr, k_out, s));
+        }
+        if (unit) {
+            HIP_OK(hipMemcpyAsync(p->sol_u + (size_t)3 * N * l0, p->w64.u, sizeof(double) * 3 * N * nr,
+                                  hipMemcpyDeviceToDevice, s));
+            if (nX)
+                HIP_OK(hipMemcpyAsync(p->sol_ue + (size_t)3 * nX * l0, p->w64.ue, sizeof(double) * 3 * nX * nr,
+                                      hipMemcpyDeviceToDevice, s));
+        }
+        HIP_OK(hipStreamSynchronize(s));
+        if (stats) {
+            for (int r = 0; r < nr; ++r) {
+                if (stats->iters) stats->iters[l0 + r] = it[r];
+                if (stats->outer_iters) stats->outer_iters[l0 + r] = outer[r];
+                if (stats->final_res) stats->final_res[l0 + r] = res[r];
+            }
+        }
+    }
+    if (stress && !device_out && vstress_dev) (void)hipFree(vstress_dev);
+    if (device_out && disp) {
+        // scale device displacements by h
+        // (small host round trip avoided: use a copy through the work buffer is unnecessary;
+        //  the caller receives voxel-unit values scaled below)
+    }
+    if (unit) p->sol_unit_basis = true;
+    if (avg_stress) {
+        if (device_out) HIP_OK(hipMemcpy(avg_stress, avg.data(), sizeof(double) * 6 * nload, hipMemcpyHostToDevice));
+        else std::memcpy(avg_stress, avg.data(), sizeof(double) * 6 * nload);
+    }
+    if (c_eff) {
+        for (int k = 0; k < 6; ++k)
+            for (int q = 0; q < 6; ++q) c_eff[6 * q + k] = avg[6 * k + q];
+    }
+    p->seconds_solve = now_s() - t0;
+    if (stats) {
+        stats->seconds_setup = p->seconds_setup;
+        stats->seconds_solve = p->seconds_solve;
+        stats->n_enriched = p->g.nX;
+        stats->n_irregular_voxels = p->g.nirr;
+        stats->n_cut_elements = p->n_cut_elements;
+        stats->n_multilabel = p->n_multilabel;
+    }
+    return status;
+}
+
+}  // namespace
+
+extern "C" {
+
+void xfft_default_options(xfft_options *opt) {
+    if (!opt) return;
+    opt->rtol = 1e-10;
+    opt->maxit = 20000;
+    opt->precision = XFFT_FP64;
+    opt->snap_eps = 1e-6;
+    opt->d0_scale = 1.0;
+    opt->inner_rtol = 1e-4;
+    opt->batch = 1;
+    opt->device = 0;
+    opt->check_every = 8;
+    opt->stream = nullptr;
+}
+
+const char *xfft_strerror(int code) {
+    switch (code) {
+        case XFFT_OK: return "ok";
+        case XFFT_NOT_CONVERGED: return "not converged within maxit";
+        case XFFT_EINVAL: return "invalid argument";
+        case XFFT_ENOMEM: return "device allocation failed";
+        case XFFT_EDEVICE: return "HIP device error";
+        case XFFT_EBREAKDOWN: return "CG breakdown (d^T A d <= 0 or not finite)";
+        default: return "unknown error";
+    }
+}
+
+void xfft_destroy(xfft_problem *p) {
+    if (!p) return;
+    (void)hipSetDevice(p->device);
+    if (p->stream) (void)hipStreamSynchronize(p->stream);
+    void *ptrs[] = {p->Ls, p->phase, p->vmat, p->irr, p->irr_j, p->irr_lab, p->jlist, p->d0, p->partial,
+                    p->scal, p->flags, p->ebar, p->sol_u, p->sol_ue, p->t64.lame, p->t64.d0is, p->t64.irr_L,
+                    p->t32.lame, p->t32.d0is, p->t32.irr_L};
+    for (void *q : ptrs)
+        if (q) (void)hipFree(q);
+    for (int a = 0; a < 3; ++a) {
+        if (p->t64.tw[a]) (void)hipFree(p->t64.tw[a]);
+        if (p->t32.tw[a]) (void)hipFree(p->t32.tw[a]);
+        if (p->t64.half[a]) (void)hipFree(p->t64.half[a]);
+        if (p->t32.half[a]) (void)hipFree(p->t32.half[a]);
+    }
+    free_work(p->w64);
+    free_work(p->w32);
+    if (p->host_flags) (void)hipHostFree(p->host_flags);
+    if (p->own_stream && p->stream) (void)hipStreamDestroy(p->stream);
+    delete p;
+}
+
+int xfft_setup(const int32_t n[3], const double len[3], const double *levelset, const int32_t *phase,
+               int32_t nphase, const double *lame, const xfft_options *opt_in, xfft_problem **out) {
+    if (!out) return XFFT_EINVAL;
+    *out = nullptr;
+    if (!n || !len || !levelset || !phase || !lame || nphase < 1) return XFFT_EINVAL;
+    for (int a = 0; a < 3; ++a)
+        if (!size_ok(n[a]) || !(len[a] > 0.0) || !std::isfinite(len[a])) return XFFT_EINVAL;
+    const double h = len[0] / n[0];
+    for (int a = 1; a < 3; ++a)
+        if (std::fabs(len[a] / n[a] - h) > 1e-12 * h) return XFFT_EINVAL;
+    if (!lame_ok(lame, nphase)) return XFFT_EINVAL;
+    {
+        const int64_t Nn = (int64_t)n[0] * n[1] * n[2];
+        for (int64_t q = 0; q < Nn; ++q)
+            if (!std::isfinite(levelset[q]) || phase[q] < 0 || phase[q] >= nphase) return XFFT_EINVAL;
+    }
+    xfft_options opt;
+    xfft_default_options(&opt);
+    if (opt_in) opt = *opt_in;
+    if (!(opt.rtol > 0.0) || opt.maxit < 1 || !(opt.snap_eps >= 0.0) || !(opt.d0_scale > 0.0) ||
+        !(opt.inner_rtol > 0.0 && opt.inner_rtol < 1.0) ||
+        (opt.precision != XFFT_FP64 && opt.precision != XFFT_MIXED))
+        return XFFT_EINVAL;
+    const double t0 = now_s();
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1 || opt.device < 0 || opt.device >= ndev)
+        return XFFT_EDEVICE;
+    if (hipSetDevice(opt.device) != hipSuccess) return XFFT_EDEVICE;
+    xfft_problem *p = new (std::nothrow) xfft_problem();
+    if (!p) return XFFT_ENOMEM;
+    p->device = opt.device;
+    p->h = h;
+    for (int a = 0; a < 3; ++a) p->len[a] = len[a];
+    p->rtol = opt.rtol; p->snap_eps = opt.snap_eps; p->d0_scale = opt.d0_scale; p->inner_rtol = opt.inner_rtol;
+    p->maxit = opt.maxit; p->precision = opt.precision; p->batch = opt.batch; p->check_every = opt.check_every;
+    if (opt.stream) {
+        p->stream = (hipStream_t)opt.stream;
+    } else {
+        if (hipStreamCreate(&p->stream) != hipSuccess) { delete p; return XFFT_EDEVICE; }
+        p->own_stream = true;
+    }
+    Geometry &g = p->g;
+    g.n0 = n[0]; g.n1 = n[1]; g.n2 = n[2]; g.nh = n[0] / 2 + 1;
+    g.N = (int64_t)n[0] * n[1] * n[2];
+    g.nphase = nphase;
+    p->lame_host.assign(lame, lame + 2 * nphase);
+    const int64_t N = g.N;
+    double *Lraw = nullptr;
+    int rc = XFFT_OK;
+    if (hipMalloc(&p->Ls, sizeof(double) * N) != hipSuccess || hipMalloc(&p->phase, sizeof(int32_t) * N) != hipSuccess ||
+        hipMalloc(&p->vmat, sizeof(int32_t) * N) != hipSuccess || hipMalloc(&Lraw, sizeof(double) * N) != hipSuccess)
+        rc = XFFT_ENOMEM;
+    if (!rc && (hipMemcpyAsync(Lraw, levelset, sizeof(double) * N, hipMemcpyHostToDevice, p->stream) != hipSuccess ||
+                hipMemcpyAsync(p->phase, phase, sizeof(int32_t) * N, hipMemcpyHostToDevice, p->stream) != hipSuccess))
+        rc = XFFT_EDEVICE;
+    if (!rc) rc = run_setup(p, Lraw);
+    if (Lraw) (void)hipFree(Lraw);
+    if (!rc) rc = compute_tables(p);
+    if (!rc) {
+        for (int a = 0; a < 3; ++a)
+            if (p->plan[a].nstages < 0) rc = XFFT_EINVAL;
+    }
+    if (!rc) {
+        SlotLayout L = slot_layout(g);
+        L.grn0 = L.total;
+        L.grn_n = green_slots(g);
+        L.eu0 = L.grn0 + L.grn_n;
+        L.eu_n = (int)((g.nX + 255) / 256);
+        L.total = L.eu0 + L.eu_n;
+        p->slots = L;
+        p->nslots = L.total;
+    }
+    if (rc) {
+        xfft_destroy(p);
+        return rc;
+    }
+    p->seconds_setup = now_s() - t0;
+    *out = p;
+    return XFFT_OK;
+}
+
+int xfft_set_lame(xfft_problem *p, const double *lame) {
+    if (!p || !lame || !lame_ok(lame, p->g.nphase)) return XFFT_EINVAL;
+    HIP_OK(hipSetDevice(p->device));
+    p->lame_host.assign(lame, lame + 2 * p->g.nphase);
+    std::vector<float> l32(2 * p->g.nphase);
+    for (int q = 0; q < 2 * p->g.nphase; ++q) l32[q] = (float)lame[q];
+    HIP_OK(hipMemcpyAsync(p->t64.lame, lame, sizeof(double) * 2 * p->g.nphase, hipMemcpyHostToDevice, p->stream));
+    HIP_OK(hipMemcpyAsync(p->t32.lame, l32.data(), sizeof(float) * 2 * p->g.nphase, hipMemcpyHostToDevice, p->stream));
+    HIP_OK(hipStreamSynchronize(p->stream));
+    p->sol_unit_basis = false;
+    return XFFT_OK;
+}
+
+int xfft_solve(xfft_problem *p, int32_t nload, const double *macro_strain, double *disp, double *stress,
+               double *avg_stress, double *c_eff, xfft_stats *stats) {
+    return solve_impl(p, nload, macro_strain, disp, stress, avg_stress, c_eff, stats, false);
+}
+
+int xfft_solve_device(xfft_problem *p, int32_t nload, const double *strain_dev, double *disp_dev,
+                      double *avg_stress_dev, void *stream, xfft_stats *stats) {
+    if (!p || nload < 1 || !strain_dev) return XFFT_EINVAL;
+    HIP_OK(hipSetDevice(p->device));
+    if (stream) HIP_OK(hipStreamSynchronize((hipStream_t)stream));
+    std::vector<double> strain(6 * nload);
+    HIP_OK(hipMemcpy(strain.data(), strain_dev, sizeof(double) * 6 * nload, hipMemcpyDeviceToHost));
+    int rc = solve_impl(p, nload, strain.data(), nullptr, nullptr, avg_stress_dev, nullptr, stats, true);
+    if (rc < 0) return rc;
+    if (disp_dev) {
+        // copy and convert to units of len on the host side of a small staging pass
+        const size_t cnt = (size_t)3 * p->g.N;
+        std::vector<double> tmp(cnt);
+        for (int l = 0; l < nload; ++l) {
+            // the last solved block holds the final loads; re-read from the stored solutions when available
+            const double *src = nullptr;
+            if (p->sol_unit_basis) src = p->sol_u + cnt * l;
+            else if (nload == 1 || !p->batch) src = p->w64.u;      // single block
+            else src = p->w64.u + cnt * l;
+            HIP_OK(hipMemcpy(tmp.data(), src, sizeof(double) * cnt, hipMemcpyDeviceToHost));
+            for (double &v : tmp) v *= p->h;
+            HIP_OK(hipMemcpy(disp_dev + cnt * l, tmp.data(), sizeof(double) * cnt, hipMemcpyHostToDevice));
+        }
+    }
+    return rc;
+}
+
+int xfft_apply_operator(xfft_problem *p, int32_t precision, const double *x, const double *macro_strain, double *y,
+                        double *avg_stress) {
+    if (!p || !x || !y || (precision != XFFT_FP64 && precision != XFFT_FP32)) return XFFT_EINVAL;
+    HIP_OK(hipSetDevice(p->device));
+    const int64_t N = p->g.N, nX = p->g.nX;
+    int rc = alloc_work<double>(p, p->w64, 1);
+    if (!rc && precision == XFFT_FP32) rc = alloc_work<float>(p, p->w32, 1);
+    if (!rc) rc = ensure_state(p, 1);
+    if (rc) return rc;
+    double eb[6] = {0, 0, 0, 0, 0, 0};
+    if (macro_strain) std::memcpy(eb, macro_strain, sizeof(eb));
+    rc = reset_state(p, 1, eb);
+    if (rc) return rc;
+    hipStream_t s = p->stream;
+    double *sum_dev = nullptr;
+    HIP_OK(hipMalloc(&sum_dev, sizeof(double) * 7));
+    if (precision == XFFT_FP64) {
+        Work<double> &w = p->w64;
+        HIP_OK(hipMemcpyAsync(w.d, x, sizeof(double) * 3 * N, hipMemcpyHostToDevice, s));
+        if (nX) HIP_OK(hipMemcpyAsync(w.de, x + 3 * N, sizeof(double) * 3 * nX, hipMemcpyHostToDevice, s));
+        launch_operator<double>(p, w, p->t64, w.d, w.de, w.z, w.ze, macro_strain != nullptr, 1.0, 1, nullptr, 0,
+                                nullptr, s);
+        launch_scalars(p, SC_SUM_ONLY, 0, 1, 0, sum_dev, s);
+        HIP_OK(hipMemcpyAsync(y, w.z, sizeof(double) * 3 * N, hipMemcpyDeviceToHost, s));
+        if (nX) HIP_OK(hipMemcpyAsync(y + 3 * N, w.ze, sizeof(double) * 3 * nX, hipMemcpyDeviceToHost, s));
+    } else {
+        Work<float> &w = p->w32;
+        std::vector<float> xf(3 * (N + nX)), yf(3 * (N + nX));
+        for (size_t q = 0; q < xf.size(); ++q) xf[q] = (float)x[q];
+        HIP_OK(hipMemcpyAsync(w.d, xf.data(), sizeof(float) * 3 * N, hipMemcpyHostToDevice, s));
+        if (nX) HIP_OK(hipMemcpyAsync(w.de, xf.data() + 3 * N, sizeof(float) * 3 * nX, hipMemcpyHostToDevice, s));
+        launch_operator<float>(p, w, p->t32, w.d, w.de, w.z, w.ze, macro_strain != nullptr, 1.0f, 1, nullptr, 0,
+                               nullptr, s);
+        launch_scalars(p, SC_SUM_ONLY, 0, 1, 0, sum_dev, s);
+        HIP_OK(hipMemcpyAsync(yf.data(), w.z, sizeof(float) * 3 * N, hipMemcpyDeviceToHost, s));
+        if (nX) HIP_OK(hipMemcpyAsync(yf.data() + 3 * N, w.ze, sizeof(float) * 3 * nX, hipMemcpyDeviceToHost, s));
+        HIP_OK(hipStreamSynchronize(s));
+        for (size_t q = 0; q < yf.size(); ++q) y[q] = (double)yf[q];
+    }
+    double sum[7];
+    HIP_OK(hipMemcpyAsync(sum, sum_dev, sizeof(sum), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    (void)hipFree(sum_dev);
+    if (avg_stress) {
+        const double V = (double)N, r2 = std::sqrt(2.0);
+        avg_stress[0] = sum[1] / V; avg_stress[1] = sum[2] / V; avg_stress[2] = sum[3] / V;
+        avg_stress[3] = r2 * sum[4] / V; avg_stress[4] = r2 * sum[5] / V; avg_stress[5] = r2 * sum[6] / V;
+    }
+    return XFFT_OK;
+}
+
+int xfft_apply_precond(xfft_problem *p, int32_t precision, const double *f, double *y, double *res2) {
+    if (!p || !f || !y || (precision != XFFT_FP64 && precision != XFFT_FP32)) return XFFT_EINVAL;
+    HIP_OK(hipSetDevice(p->device));
+    const int64_t N = p->g.N, nX = p->g.nX;
+    int rc = alloc_work<double>(p, p->w64, 1);
+    if (!rc && precision == XFFT_FP32) rc = alloc_work<float>(p, p->w32, 1);
+    if (!rc) rc = ensure_state(p, 1);
+    if (rc) return rc;
+    rc = reset_state(p, 1, nullptr);
+    if (rc) return rc;
+    hipStream_t s = p->stream;
+    double *sum_dev = nullptr;
+    HIP_OK(hipMalloc(&sum_dev, sizeof(double) * 7));
+    if (precision == XFFT_FP64) {
+        Work<double> &w = p->w64;
+        HIP_OK(hipMemcpyAsync(w.f, f, sizeof(double) * 3 * N, hipMemcpyHostToDevice, s));
+        if (nX) HIP_OK(hipMemcpyAsync(w.fe, f + 3 * N, sizeof(double) * 3 * nX, hipMemcpyHostToDevice, s));
+        launch_green_forward<double>(p, w, p->t64, w.f, nullptr, 1, nullptr, 0, s);
+        launch_enr_update<double>(p, w, 0, w.ze, 1, nullptr, 0, s);
+        launch_green_inverse<double>(p, w, p->t64, 0, w.z, 1, nullptr, 0, s);
+        launch_scalars(p, SC_SUM_GREEN, 0, 1, 0, sum_dev, s);
+        HIP_OK(hipMemcpyAsync(y, w.z, sizeof(double) * 3 * N, hipMemcpyDeviceToHost, s));
+        if (nX) HIP_OK(hipMemcpyAsync(y + 3 * N, w.ze, sizeof(double) * 3 * nX, hipMemcpyDeviceToHost, s));
+    } else {
+        Work<float> &w = p->w32;
+        std::vector<float> ff(3 * (N + nX)), yf(3 * (N + nX));
+        for (size_t q = 0; q < ff.size(); ++q) ff[q] = (float)f[q];
+        HIP_OK(hipMemcpyAsync(w.f, ff.data(), sizeof(float) * 3 * N, hipMemcpyHostToDevice, s));
+        if (nX) HIP_OK(hipMemcpyAsync(w.fe, ff.data() + 3 * N, sizeof(float) * 3 * nX, hipMemcpyHostToDevice, s));
+        launch_green_forward<float>(p, w, p->t32, w.f, nullptr, 1, nullptr, 0, s);
+        launch_enr_update<float>(p, w, 0, w.ze, 1, nullptr, 0, s);
+        launch_green_inverse<float>(p, w, p->t32, 0, w.z, 1, nullptr, 0, s);
+        launch_scalars(p, SC_SUM_GREEN, 0, 1, 0, sum_dev, s);
+        HIP_OK(hipMemcpyAsync(yf.data(), w.z, sizeof(float) * 3 * N, hipMemcpyDeviceToHost, s));
+        if (nX) HIP_OK(hipMemcpyAsync(yf.data() + 3 * N, w.ze, sizeof(float) * 3 * nX, hipMemcpyDeviceToHost, s));
+        HIP_OK(hipStreamSynchronize(s));
+        for (size_t q = 0; q < yf.size(); ++q) y[q] = (double)yf[q];
+    }
+    double sum[7];
+    HIP_OK(hipMemcpyAsync(sum, sum_dev, sizeof(sum), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    (void)hipFree(sum_dev);
+    if (res2) *res2 = sum[0];
+    return XFFT_OK;
+}
+
+int xfft_get_layout(xfft_problem *p, int64_t *info, int64_t *jlist, double *d0) {
+    if (!p || !info) return XFFT_EINVAL;
+    HIP_OK(hipSetDevice(p->device));
+    info[0] = p->g.N;
+    info[1] = p->g.nX;
+    info[2] = p->g.nirr;
+    info[3] = p->n_cut_elements;
+    info[4] = p->n_multilabel;
+    info[5] = p->g.nphase;
+    if (p->g.nX > 0 && jlist) {
+        std::vector<int32_t> tmp(p->g.nX);
+        HIP_OK(hipMemcpy(tmp.data(), p->jlist, sizeof(int32_t) * p->g.nX, hipMemcpyDeviceToHost));
+        for (int64_t q = 0; q < p->g.nX; ++q) jlist[q] = tmp[q];
+    }
+    if (p->g.nX > 0 && d0) HIP_OK(hipMemcpy(d0, p->d0, sizeof(double) * p->g.nX, hipMemcpyDeviceToHost));
+    return XFFT_OK;
+}
+
+int xfft_grad_lame(xfft_problem *p, const double *dL_dC, double *grad, double *dC_out) {
+    (void)p; (void)dL_dC; (void)grad; (void)dC_out;
+    return XFFT_EINVAL;
+}
+
+int xfft_batch_solve(xfft_problem *const *ps, int32_t nprob, double *c_eff, xfft_stats *stats) {
+    if (!ps || nprob < 1 || !c_eff) return XFFT_EINVAL;
+    double E[36];
+    for (int k = 0; k < 36; ++k) E[k] = (k % 7 == 0) ? 1.0 : 0.0;
+    int status = XFFT_OK;
+    for (int i = 0; i < nprob; ++i) {
+        int rc = xfft_solve(ps[i], 6, E, nullptr, nullptr, nullptr, c_eff + 36 * i, stats ? stats + i : nullptr);
+        if (rc < 0) return rc;
+        if (rc == XFFT_NOT_CONVERGED) status = rc;
+    }
+    return status;
+}
+
+}  // extern "C"

@@ -1,0 +1,184 @@
+// Internal declarations of the X-FFT GPU library (gfx950).
+//
+// Geometry conventions of the device code (voxel units, h = 1):
+//   node (i, j, k) -> flat index i + n0 * (j + n1 * k), periodic;
+//   voxel (i, j, k) has corners (i + dx, j + dy, k + dz), corner code
+//   c = dx | dy << 1 | dz << 2;
+//   the six P1 elements of a voxel (Sec. 3) are the Kuhn tetrahedra that share
+//   the diagonal corner 0 -> corner 7: for an axis permutation (p0, p1, p2) the
+//   path 0 -> e_p0 -> e_p0 + e_p1 -> (1, 1, 1).  Barycentric gradients along the
+//   path are -e_p0, e_p0 - e_p1, e_p1 - e_p2, e_p2 and the volume is 1/6.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <vector>
+
+namespace xfft {
+
+// ------------------------------------------------------------------ Kuhn table
+// permutations in lexicographic order; PERM[t][s] = axis of step s
+__host__ __device__ constexpr int perm_axis(int t, int s) {
+    // (0,1,2) (0,2,1) (1,0,2) (1,2,0) (2,0,1) (2,1,0)
+    return (t == 0) ? (s == 0 ? 0 : s == 1 ? 1 : 2)
+         : (t == 1) ? (s == 0 ? 0 : s == 1 ? 2 : 1)
+         : (t == 2) ? (s == 0 ? 1 : s == 1 ? 0 : 2)
+         : (t == 3) ? (s == 0 ? 1 : s == 1 ? 2 : 0)
+         : (t == 4) ? (s == 0 ? 2 : s == 1 ? 0 : 1)
+         :            (s == 0 ? 2 : s == 1 ? 1 : 0);
+}
+// corner code of vertex v (0..3) of tet t
+__host__ __device__ constexpr int tet_corner(int t, int v) {
+    return v == 0 ? 0
+         : v == 1 ? (1 << perm_axis(t, 0))
+         : v == 2 ? ((1 << perm_axis(t, 0)) | (1 << perm_axis(t, 1)))
+         : 7;
+}
+
+// ------------------------------------------------------------------ complex
+template <typename T> struct cpx { T x, y; };
+
+template <typename T> __device__ __forceinline__ cpx<T> cmul(cpx<T> a, cpx<T> b) {
+    return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <typename T> __device__ __forceinline__ cpx<T> cadd(cpx<T> a, cpx<T> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename T> __device__ __forceinline__ cpx<T> csub(cpx<T> a, cpx<T> b) { return {a.x - b.x, a.y - b.y}; }
+
+// ------------------------------------------------------------------ FFT plan
+struct FftPlan {
+    int n;            // line length
+    int nstages;
+    int radix[16];    // radices applied in order (4, 2, 3)
+};
+FftPlan make_plan(int n);
+
+// ------------------------------------------------------------------ block reduction
+// Sums NV doubles over the block; result valid in thread 0. red must hold
+// NV * (blockDim.x / 64) doubles of shared memory.
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV], double *red) {
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+        double s = v[q];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+        v[q] = s;
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    __syncthreads();
+    if (lane == 0) {
+#pragma unroll
+        for (int q = 0; q < NV; ++q) red[wave * NV + q] = v[q];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int q = 0; q < NV; ++q) {
+            double s = 0.0;
+            for (int w = 0; w < nw; ++w) s += red[w * NV + q];
+            v[q] = s;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ problem
+constexpr int NPART = 8;   // doubles per partial-sum slot: [0] dot, [1..6] stress integral
+
+struct Geometry {
+    int n0, n1, n2, nh;     // nh = n0 / 2 + 1
+    int64_t N;              // nodes = voxels
+    int64_t nX;             // enriched nodes
+    int64_t nirr;           // irregular voxels
+    int nphase;
+};
+
+// Per-precision device tables.
+template <typename T> struct Tables {
+    T *lame = nullptr;       // [nphase][2]
+    T *d0is = nullptr;       // [nX] D0^-1/2
+    T *irr_L = nullptr;      // [nirr][8] snapped corner level set of irregular voxels
+    cpx<T> *tw[3] = {nullptr, nullptr, nullptr};   // twiddles exp(-2 pi i t / n_axis)
+    T *half[3] = {nullptr, nullptr, nullptr};      // [n_axis][2]: sin, cos of pi k / n_axis
+};
+
+// Work fields of one precision for up to `cap` right-hand sides.
+template <typename T> struct Work {
+    int cap = 0;
+    T *u = nullptr, *f = nullptr, *d = nullptr, *z = nullptr;          // [cap][3][N]
+    T *ue = nullptr, *fe = nullptr, *de = nullptr, *ze = nullptr;      // [cap][3][nX]
+    cpx<T> *spec = nullptr;                                            // [cap][3][n2][n1][nh]
+    T *cutbuf = nullptr;                                               // [cap][nirr][8][6]
+};
+
+// Partial-sum slot layout per right-hand side.
+struct SlotLayout {
+    int fe0, fe_n;      // regular-voxel operator blocks
+    int cut0, cut_n;    // irregular-voxel blocks
+    int enr0, enr_n;    // enriched gather blocks
+    int grn0, grn_n;    // Green (z pass) blocks
+    int eu0, eu_n;      // enriched residual blocks
+    int total;
+    int kz;             // planes per operator block
+    int tiles_x, tiles_y, zchunks;
+};
+
+struct Scalars {           // per right-hand side, device resident
+    double res2, res2_0, alpha, beta;
+    double sigma[6];
+    double tol;            // tolerance of eq. stoppingCriterion (criterion 0)
+    double tol_inner;      // residual reduction of an inner refinement solve (criterion 1)
+};
+
+struct Flags {
+    int active[2];         // parity-buffered "iteration runs" flag
+    int iters;
+    int conv;
+    int breakdown;
+    int pad[3];            // pad[0]: outer (refinement) loop converged
+};
+
+}  // namespace xfft
+
+// The opaque handle.
+struct xfft_problem {
+    xfft::Geometry g;
+    double h = 1.0;
+    double len[3];
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    // options
+    double rtol, snap_eps, d0_scale, inner_rtol;
+    int maxit, precision, batch, check_every;
+    // geometry (device)
+    double *Ls = nullptr;          // snapped level set, voxel units [N]
+    int32_t *phase = nullptr;      // [N]
+    int32_t *vmat = nullptr;       // [N] material (>= 0) or -(irregular index + 1)
+    int32_t *irr = nullptr;        // [nirr] voxel of each irregular voxel
+    int32_t *irr_j = nullptr;      // [nirr][8] enriched index per corner or -1
+    int32_t *irr_lab = nullptr;    // [nirr][6][2] element labels: uncut (both) or (+ side, - side)
+    int32_t *jlist = nullptr;      // [nX]
+    double *d0 = nullptr;          // [nX]
+    int64_t n_cut_elements = 0, n_multilabel = 0;
+    std::vector<double> lame_host;
+    xfft::Tables<double> t64;
+    xfft::Tables<float> t32;
+    xfft::FftPlan plan[3];
+    xfft::SlotLayout slots;
+    // work space
+    xfft::Work<double> w64;
+    xfft::Work<float> w32;
+    double *partial = nullptr;     // [cap][nslots][NPART]
+    int part_cap = 0, nslots = 0;
+    xfft::Scalars *scal = nullptr; // [cap]
+    xfft::Flags *flags = nullptr;  // [cap]
+    double *ebar = nullptr;        // [cap][6]
+    int *host_flags = nullptr;     // pinned mirror for polling
+    int scal_cap = 0;
+    // solutions of the last solve (FP64, voxel units) for gradients
+    double *sol_u = nullptr, *sol_ue = nullptr;
+    int sol_nload = 0;
+    bool sol_unit_basis = false;
+    double seconds_setup = 0.0, seconds_solve = 0.0;
+};

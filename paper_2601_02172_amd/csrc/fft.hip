@@ -1,0 +1,453 @@
+// Green operator of the reference FE stiffness (eqs. constantCoefficientPreconditioner,
+// GreenHermitian) applied by real 3-D FFT, in five passes over HBM:
+//   x forward  r2c along x of row pairs (two real rows packed as one complex
+//              line), fused with the residual update f -= alpha z;
+//   y forward  complex FFT along y;
+//   z + Green  complex FFT along z, per-frequency 3x3 solve with the symbol of
+//              A11^0, Parseval partial of f^T G f, inverse FFT along z;
+//   y inverse;
+//   x inverse  c2r of row pairs fused with the CG update of d and u.
+// Every line FFT is an LDS Stockham autosort transform with radices 4, 2, 3.
+//
+// Symbol (derived from eq. GreenHermitian for the six Kuhn elements of the
+// reference voxel, identity material; real and symmetric): with
+// theta_a = 2 pi xi_a / n_a, s_a = sin(theta_a / 2),
+//   S_aa = 2 sum_b s_b^2 + 2 s_a^2,
+//   S_ab = (2/3) s_a s_b [2 cos(phi_ab) + cos(phi_ab + theta_c)],
+//   phi_ab = (theta_a + theta_b) / 2, {a, b, c} = {0, 1, 2};
+// S(0) = 0 maps the zero frequency to zero (mean-free FE field).
+#include "kernels.h"
+
+namespace xfft {
+
+FftPlan make_plan(int n) {
+    FftPlan p{};
+    p.n = n;
+    int m = n, k = 0;
+    while (m % 4 == 0) { p.radix[k++] = 4; m /= 4; }
+    while (m % 2 == 0) { p.radix[k++] = 2; m /= 2; }
+    while (m % 3 == 0) { p.radix[k++] = 3; m /= 3; }
+    p.nstages = (m == 1) ? k : -1;
+    return p;
+}
+
+namespace {
+
+constexpr int MAXB = 4;
+
+template <typename T, bool INV>
+__device__ __forceinline__ void butterfly(cpx<T> (&v)[4], int R) {
+    if (R == 2) {
+        const cpx<T> a = v[0], b = v[1];
+        v[0] = cadd(a, b);
+        v[1] = csub(a, b);
+    } else if (R == 4) {
+        const cpx<T> t0 = cadd(v[0], v[2]), t1 = csub(v[0], v[2]);
+        const cpx<T> t2 = cadd(v[1], v[3]), t3 = csub(v[1], v[3]);
+        // forward: multiply t3 by -i; inverse: by +i
+        const cpx<T> t3r = INV ? cpx<T>{-t3.y, t3.x} : cpx<T>{t3.y, -t3.x};
+        v[0] = cadd(t0, t2);
+        v[2] = csub(t0, t2);
+        v[1] = cadd(t1, t3r);
+        v[3] = csub(t1, t3r);
+    } else {  // R == 3
+        const T c = (T)0.86602540378443864676;   // sqrt(3)/2
+        const cpx<T> a = v[0];
+        const cpx<T> t1 = cadd(v[1], v[2]), t2 = csub(v[1], v[2]);
+        const cpx<T> m = {a.x - (T)0.5 * t1.x, a.y - (T)0.5 * t1.y};
+        // forward: y1 = m - i c t2, y2 = m + i c t2 (inverse swaps)
+        const cpx<T> it2 = INV ? cpx<T>{-c * t2.y, c * t2.x} : cpx<T>{c * t2.y, -c * t2.x};
+        v[0] = cadd(a, t1);
+        v[1] = cadd(m, it2);
+        v[2] = csub(m, it2);
+    }
+}
+
+// In-place Stockham FFT of `nlines` lines stored at buf + line * lstride.
+template <typename T, bool INV>
+__device__ void lds_fft(cpx<T> *buf, int nlines, int lstride, const FftPlan &pl, const cpx<T> *__restrict__ tw) {
+    const int n = pl.n;
+    int Ns = 1;
+    for (int st = 0; st < pl.nstages; ++st) {
+        const int R = pl.radix[st];
+        const int nb = n / R;
+        const int total = nlines * nb;
+        const int tws = n / (Ns * R);
+        cpx<T> v[MAXB][4];
+#pragma unroll
+        for (int i = 0; i < MAXB; ++i) {
+            const int b = threadIdx.x + i * blockDim.x;
+            if (b < total) {
+                const int line = b / nb, jj = b - line * nb;
+                const int k = jj % Ns;
+                const cpx<T> *Lp = buf + line * lstride;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    if (r < R) {
+                        cpx<T> x = Lp[jj + r * nb];
+                        if (r > 0) {
+                            cpx<T> w = tw[r * k * tws];
+                            if (INV) w.y = -w.y;
+                            x = cmul(x, w);
+                        }
+                        v[i][r] = x;
+                    }
+                }
+                butterfly<T, INV>(v[i], R);
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < MAXB; ++i) {
+            const int b = threadIdx.x + i * blockDim.x;
+            if (b < total) {
+                const int line = b / nb, jj = b - line * nb;
+                const int k = jj % Ns;
+                cpx<T> *Lp = buf + line * lstride;
+                const int base = (jj / Ns) * Ns * R + k;
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    if (r < R) Lp[base + r * Ns] = v[i][r];
+            }
+        }
+        __syncthreads();
+        Ns *= R;
+    }
+}
+
+struct FftArgs {
+    int n0, n1, n2, nh;
+    int64_t N, specN;        // nodes; complex entries per component spectrum... per rhs: 3 * specN
+    const Flags *flags;
+    int parity;
+    const Scalars *scal;
+    double *partial;
+    int nslots, slot0;
+};
+
+__device__ __forceinline__ bool active_rhs(const FftArgs &A, int r) {
+    return A.flags == nullptr || A.flags[r].active[A.parity] != 0;
+}
+
+// ---------------------------------------------------------------- x forward (r2c)
+template <typename T>
+__global__ __launch_bounds__(256) void k_fft_x_fwd(FftArgs A, FftPlan pl, const cpx<T> *tw, T *f, const T *z,
+                                                    cpx<T> *spec, int pairs_per_block) {
+    extern __shared__ unsigned char smem_raw[];
+    cpx<T> *sh = reinterpret_cast<cpx<T> *>(smem_raw);
+    const int r = blockIdx.y;
+    if (!active_rhs(A, r)) return;
+    const int n0 = A.n0, nh = A.nh;
+    const int lstride = n0 + 1;
+    const int64_t npairs = (int64_t)3 * A.n2 * A.n1 / 2;
+    const T alpha = z ? (T)A.scal[r].alpha : (T)0;
+    T *fr = f + (int64_t)r * 3 * A.N;
+    const T *zr = z ? z + (int64_t)r * 3 * A.N : nullptr;
+    cpx<T> *sr = spec + (int64_t)r * 3 * A.specN;
+    const int64_t p0 = (int64_t)blockIdx.x * pairs_per_block;
+    for (int idx = threadIdx.x; idx < pairs_per_block * n0; idx += blockDim.x) {
+        const int lp = idx / n0, x = idx - lp * n0;
+        const int64_t pr = p0 + lp;
+        T a = 0, b = 0;
+        if (pr < npairs) {
+            const int64_t o0 = (2 * pr) * n0 + x, o1 = o0 + n0;
+            a = fr[o0];
+            b = fr[o1];
+            if (zr) {
+                a -= alpha * zr[o0];
+                b -= alpha * zr[o1];
+                fr[o0] = a;
+                fr[o1] = b;
+            }
+        }
+        sh[lp * lstride + x] = {a, b};
+    }
+    __syncthreads();
+    lds_fft<T, false>(sh, pairs_per_block, lstride, pl, tw);
+    for (int idx = threadIdx.x; idx < pairs_per_block * nh; idx += blockDim.x) {
+        const int lp = idx / nh, kx = idx - lp * nh;
+        const int64_t pr = p0 + lp;
+        if (pr < npairs) {
+            const cpx<T> Zk = sh[lp * lstride + kx];
+            const cpx<T> Zm = sh[lp * lstride + (kx == 0 ? 0 : n0 - kx)];
+            const cpx<T> Av = {(T)0.5 * (Zk.x + Zm.x), (T)0.5 * (Zk.y - Zm.y)};
+            const cpx<T> Bv = {(T)0.5 * (Zk.y + Zm.y), (T)-0.5 * (Zk.x - Zm.x)};
+            sr[(2 * pr) * nh + kx] = Av;
+            sr[(2 * pr + 1) * nh + kx] = Bv;
+        }
+    }
+}
+
+// ---------------------------------------------------------------- y pass
+template <typename T, bool INV>
+__global__ __launch_bounds__(256) void k_fft_y(FftArgs A, FftPlan pl, const cpx<T> *tw, cpx<T> *spec, int tk) {
+    extern __shared__ unsigned char smem_raw[];
+    cpx<T> *sh = reinterpret_cast<cpx<T> *>(smem_raw);
+    const int r = blockIdx.y;
+    if (!active_rhs(A, r)) return;
+    const int n1 = A.n1, nh = A.nh;
+    const int lstride = n1 + 1;
+    const int ntiles = (nh + tk - 1) / tk;
+    const int tile = blockIdx.x % ntiles;
+    const int plane = blockIdx.x / ntiles;          // c * n2 + k
+    const int kx0 = tile * tk;
+    cpx<T> *base = spec + (int64_t)r * 3 * A.specN + (int64_t)plane * n1 * nh;
+    for (int idx = threadIdx.x; idx < tk * n1; idx += blockDim.x) {
+        const int kl = idx % tk, yy = idx / tk;
+        const int kx = kx0 + kl;
+        sh[kl * lstride + yy] = (kx < nh) ? base[(int64_t)yy * nh + kx] : cpx<T>{0, 0};
+    }
+    __syncthreads();
+    lds_fft<T, INV>(sh, tk, lstride, pl, tw);
+    for (int idx = threadIdx.x; idx < tk * n1; idx += blockDim.x) {
+        const int kl = idx % tk, yy = idx / tk;
+        const int kx = kx0 + kl;
+        if (kx < nh) base[(int64_t)yy * nh + kx] = sh[kl * lstride + yy];
+    }
+}
+
+// ---------------------------------------------------------------- z pass with Green multiply
+template <typename T>
+__device__ __forceinline__ void green_apply(T s0, T c0, T s1, T c1, T s2, T c2, cpx<T> (&f)[3], bool zero) {
+    // half-angle sines/cosines per axis -> symbol entries
+    const T q0 = s0 * s0, q1 = s1 * s1, q2 = s2 * s2;
+    const T sum = q0 + q1 + q2;
+    const T S00 = (T)2 * sum + (T)2 * q0, S11 = (T)2 * sum + (T)2 * q1, S22 = (T)2 * sum + (T)2 * q2;
+    // cos(theta) = 1 - 2 s^2, sin(theta) = 2 s c; cos(phi_ab) with phi_ab = half-angle sum
+    const T ct0 = (T)1 - (T)2 * q0, st0 = (T)2 * s0 * c0;
+    const T ct1 = (T)1 - (T)2 * q1, st1 = (T)2 * s1 * c1;
+    const T ct2 = (T)1 - (T)2 * q2, st2 = (T)2 * s2 * c2;
+    const T cp01 = c0 * c1 - s0 * s1, sp01 = s0 * c1 + c0 * s1;
+    const T cp02 = c0 * c2 - s0 * s2, sp02 = s0 * c2 + c0 * s2;
+    const T cp12 = c1 * c2 - s1 * s2, sp12 = s1 * c2 + c1 * s2;
+    const T k23 = (T)(2.0 / 3.0);
+    const T S01 = k23 * s0 * s1 * ((T)2 * cp01 + (cp01 * ct2 - sp01 * st2));
+    const T S02 = k23 * s0 * s2 * ((T)2 * cp02 + (cp02 * ct1 - sp02 * st1));
+    const T S12 = k23 * s1 * s2 * ((T)2 * cp12 + (cp12 * ct0 - sp12 * st0));
+    // inverse of the symmetric 3x3 matrix by its adjugate
+    const T A00 = S11 * S22 - S12 * S12, A01 = S02 * S12 - S01 * S22, A02 = S01 * S12 - S02 * S11;
+    const T A11 = S00 * S22 - S02 * S02, A12 = S01 * S02 - S00 * S12, A22 = S00 * S11 - S01 * S01;
+    const T det = S00 * A00 + S01 * A01 + S02 * A02;
+    const T inv = zero ? (T)0 : (T)1 / det;
+    cpx<T> y[3];
+    y[0] = {inv * (A00 * f[0].x + A01 * f[1].x + A02 * f[2].x), inv * (A00 * f[0].y + A01 * f[1].y + A02 * f[2].y)};
+    y[1] = {inv * (A01 * f[0].x + A11 * f[1].x + A12 * f[2].x), inv * (A01 * f[0].y + A11 * f[1].y + A12 * f[2].y)};
+    y[2] = {inv * (A02 * f[0].x + A12 * f[1].x + A22 * f[2].x), inv * (A02 * f[0].y + A12 * f[1].y + A22 * f[2].y)};
+    f[0] = y[0];
+    f[1] = y[1];
+    f[2] = y[2];
+}
+
+template <typename T>
+__global__ __launch_bounds__(512) void k_fft_z_green(FftArgs A, FftPlan pl, const cpx<T> *tw, const T *h0,
+                                                      const T *h1, const T *h2, cpx<T> *spec, int tk) {
+    extern __shared__ unsigned char smem_raw[];
+    cpx<T> *sh = reinterpret_cast<cpx<T> *>(smem_raw);
+    __shared__ double red[8];
+    const int r = blockIdx.y;
+    if (!active_rhs(A, r)) return;
+    const int n1 = A.n1, n2 = A.n2, nh = A.nh;
+    const int lstride = n2 + 1;
+    const int ntiles = (nh + tk - 1) / tk;
+    const int tile = blockIdx.x % ntiles;
+    const int ky = blockIdx.x / ntiles;
+    const int kx0 = tile * tk;
+    cpx<T> *base = spec + (int64_t)r * 3 * A.specN;
+    const int64_t zstride = (int64_t)n1 * nh;
+    for (int idx = threadIdx.x; idx < 3 * tk * n2; idx += blockDim.x) {
+        const int kl = idx % tk, rest = idx / tk;
+        const int zz = rest % n2, c = rest / n2;
+        const int kx = kx0 + kl;
+        sh[(c * tk + kl) * lstride + zz] =
+            (kx < nh) ? base[(int64_t)c * A.specN + zz * zstride + (int64_t)ky * nh + kx] : cpx<T>{0, 0};
+    }
+    __syncthreads();
+    lds_fft<T, false>(sh, 3 * tk, lstride, pl, tw);
+    double part = 0.0;
+    const T scale = (T)(1.0 / ((double)A.n0 * (double)n1 * (double)n2));
+    for (int idx = threadIdx.x; idx < tk * n2; idx += blockDim.x) {
+        const int kl = idx % tk, zz = idx / tk;
+        const int kx = kx0 + kl;
+        if (kx < nh) {
+            cpx<T> f[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) f[c] = sh[(c * tk + kl) * lstride + zz];
+            const cpx<T> f0[3] = {f[0], f[1], f[2]};
+            green_apply<T>(h0[2 * kx], h0[2 * kx + 1], h1[2 * ky], h1[2 * ky + 1], h2[2 * zz], h2[2 * zz + 1], f,
+                           kx == 0 && ky == 0 && zz == 0);
+            double q = 0.0;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                f[c].x *= scale;
+                f[c].y *= scale;
+                q += (double)f0[c].x * (double)f[c].x + (double)f0[c].y * (double)f[c].y;
+                sh[(c * tk + kl) * lstride + zz] = f[c];
+            }
+            const double wgt = (kx == 0 || 2 * kx == A.n0) ? 1.0 : 2.0;
+            part += wgt * q;
+        }
+    }
+    __syncthreads();
+    lds_fft<T, true>(sh, 3 * tk, lstride, pl, tw);
+    for (int idx = threadIdx.x; idx < 3 * tk * n2; idx += blockDim.x) {
+        const int kl = idx % tk, rest = idx / tk;
+        const int zz = rest % n2, c = rest / n2;
+        const int kx = kx0 + kl;
+        if (kx < nh) base[(int64_t)c * A.specN + zz * zstride + (int64_t)ky * nh + kx] = sh[(c * tk + kl) * lstride + zz];
+    }
+    double v[1] = {part};
+    block_sum<1>(v, red);
+    if (threadIdx.x == 0) {
+        double *P = A.partial + ((int64_t)r * A.nslots + A.slot0 + blockIdx.x) * NPART;
+        P[0] = v[0];
+#pragma unroll
+        for (int q = 1; q < 7; ++q) P[q] = 0.0;
+    }
+}
+
+// ---------------------------------------------------------------- x inverse (c2r) + CG update
+template <typename T>
+__global__ __launch_bounds__(256) void k_fft_x_inv(FftArgs A, FftPlan pl, const cpx<T> *tw, const cpx<T> *spec,
+                                                    int mode, T *out, T *u, T *d, int pairs_per_block) {
+    extern __shared__ unsigned char smem_raw[];
+    cpx<T> *sh = reinterpret_cast<cpx<T> *>(smem_raw);
+    const int r = blockIdx.y;
+    if (!active_rhs(A, r)) return;
+    const int n0 = A.n0, nh = A.nh;
+    const int lstride = n0 + 1;
+    const int64_t npairs = (int64_t)3 * A.n2 * A.n1 / 2;
+    const cpx<T> *sr = spec + (int64_t)r * 3 * A.specN;
+    const int64_t p0 = (int64_t)blockIdx.x * pairs_per_block;
+    for (int idx = threadIdx.x; idx < pairs_per_block * n0; idx += blockDim.x) {
+        const int lp = idx / n0, k = idx - lp * n0;
+        const int64_t pr = p0 + lp;
+        cpx<T> Zv = {0, 0};
+        if (pr < npairs) {
+            const bool lo = k < nh;
+            const int kk = lo ? k : n0 - k;
+            cpx<T> Av = sr[(2 * pr) * nh + kk], Bv = sr[(2 * pr + 1) * nh + kk];
+            if (!lo) { Av.y = -Av.y; Bv.y = -Bv.y; }
+            Zv = {Av.x - Bv.y, Av.y + Bv.x};
+        }
+        sh[lp * lstride + k] = Zv;
+    }
+    __syncthreads();
+    lds_fft<T, true>(sh, pairs_per_block, lstride, pl, tw);
+    const int64_t rN = (int64_t)r * 3 * A.N;
+    T alpha = 0, beta = 0;
+    if (mode == 1) { alpha = (T)A.scal[r].alpha; beta = (T)A.scal[r].beta; }
+    for (int idx = threadIdx.x; idx < pairs_per_block * n0; idx += blockDim.x) {
+        const int lp = idx / n0, x = idx - lp * n0;
+        const int64_t pr = p0 + lp;
+        if (pr < npairs) {
+            const cpx<T> yv = sh[lp * lstride + x];
+            const int64_t o0 = rN + (2 * pr) * n0 + x, o1 = o0 + n0;
+            if (mode == 0) {
+                out[o0] = yv.x;
+                out[o1] = yv.y;
+            } else if (mode == 1) {
+                const T d0 = d[o0], d1 = d[o1];
+                u[o0] += alpha * d0;
+                u[o1] += alpha * d1;
+                d[o0] = yv.x + beta * d0;
+                d[o1] = yv.y + beta * d1;
+            } else {
+                d[o0] = yv.x;
+                d[o1] = yv.y;
+            }
+        }
+    }
+}
+
+template <typename T> int pairs_for(int n0) {
+    // limit: butterflies per stage <= MAXB * 256 (radix 2 worst case) and LDS <= 64 KiB
+    int p = (MAXB * 256 * 2) / n0;
+    const int lds_cap = (int)(65536 / ((n0 + 1) * sizeof(cpx<T>)));
+    if (p > lds_cap) p = lds_cap;
+    if (p < 1) p = 1;
+    return p;
+}
+template <typename T> int tk_for(int n, int lines_factor, int threads) {
+    int t = (MAXB * threads * 2) / (n * lines_factor);
+    const int lds_cap = (int)(65536 / ((n + 1) * sizeof(cpx<T>) * lines_factor));
+    if (t > lds_cap) t = lds_cap;
+    if (t > 16) t = 16;
+    if (t < 1) t = 1;
+    return t;
+}
+
+template <typename T>
+FftArgs fft_args(xfft_problem *p, const Flags *flags, int parity) {
+    FftArgs A;
+    A.n0 = p->g.n0; A.n1 = p->g.n1; A.n2 = p->g.n2; A.nh = p->g.nh;
+    A.N = p->g.N;
+    A.specN = (int64_t)p->g.n2 * p->g.n1 * p->g.nh;
+    A.flags = flags; A.parity = parity; A.scal = p->scal;
+    A.partial = p->partial; A.nslots = p->nslots; A.slot0 = 0;
+    return A;
+}
+
+}  // namespace
+
+// The z pass uses the FP64 tile width in both precisions so that its number of
+// blocks (= partial-sum slots) does not depend on the precision.
+static int tk_z(const Geometry &g) { return tk_for<double>(g.n2, 3, 512); }
+
+int green_slots(const Geometry &g) { return g.n1 * ((g.nh + tk_z(g) - 1) / tk_z(g)); }
+
+template <typename T>
+void launch_green_forward(xfft_problem *p, Work<T> &w, const Tables<T> &tb, T *f, const T *z, int nrhs,
+                          const Flags *flags, int parity, hipStream_t s) {
+    const Geometry &g = p->g;
+    FftArgs A = fft_args<T>(p, flags, parity);
+    {
+        const int pp = pairs_for<T>(g.n0);
+        const int64_t npairs = (int64_t)3 * g.n2 * g.n1 / 2;
+        dim3 grid((unsigned)((npairs + pp - 1) / pp), nrhs);
+        const size_t lds = (size_t)pp * (g.n0 + 1) * sizeof(cpx<T>);
+        k_fft_x_fwd<T><<<grid, 256, lds, s>>>(A, p->plan[0], tb.tw[0], f, z, w.spec, pp);
+    }
+    {
+        const int tk = tk_for<T>(g.n1, 1, 256);
+        dim3 grid(3 * g.n2 * ((g.nh + tk - 1) / tk), nrhs);
+        const size_t lds = (size_t)tk * (g.n1 + 1) * sizeof(cpx<T>);
+        k_fft_y<T, false><<<grid, 256, lds, s>>>(A, p->plan[1], tb.tw[1], w.spec, tk);
+    }
+    {
+        const int tk = tk_z(g);
+        A.slot0 = p->slots.grn0;
+        dim3 grid(g.n1 * ((g.nh + tk - 1) / tk), nrhs);
+        const size_t lds = (size_t)3 * tk * (g.n2 + 1) * sizeof(cpx<T>);
+        k_fft_z_green<T><<<grid, 512, lds, s>>>(A, p->plan[2], tb.tw[2], tb.half[0], tb.half[1], tb.half[2], w.spec,
+                                                 tk);
+    }
+    {
+        const int tk = tk_for<T>(g.n1, 1, 256);
+        dim3 grid(3 * g.n2 * ((g.nh + tk - 1) / tk), nrhs);
+        const size_t lds = (size_t)tk * (g.n1 + 1) * sizeof(cpx<T>);
+        k_fft_y<T, true><<<grid, 256, lds, s>>>(A, p->plan[1], tb.tw[1], w.spec, tk);
+    }
+}
+
+template <typename T>
+void launch_green_inverse(xfft_problem *p, Work<T> &w, const Tables<T> &tb, int mode, T *out, int nrhs,
+                          const Flags *flags, int parity, hipStream_t s) {
+    const Geometry &g = p->g;
+    FftArgs A = fft_args<T>(p, flags, parity);
+    const int pp = pairs_for<T>(g.n0);
+    const int64_t npairs = (int64_t)3 * g.n2 * g.n1 / 2;
+    dim3 grid((unsigned)((npairs + pp - 1) / pp), nrhs);
+    const size_t lds = (size_t)pp * (g.n0 + 1) * sizeof(cpx<T>);
+    k_fft_x_inv<T><<<grid, 256, lds, s>>>(A, p->plan[0], tb.tw[0], w.spec, mode, out, w.u, w.d, pp);
+}
+
+template void launch_green_forward<double>(xfft_problem *, Work<double> &, const Tables<double> &, double *,
+                                           const double *, int, const Flags *, int, hipStream_t);
+template void launch_green_forward<float>(xfft_problem *, Work<float> &, const Tables<float> &, float *,
+                                          const float *, int, const Flags *, int, hipStream_t);
+template void launch_green_inverse<double>(xfft_problem *, Work<double> &, const Tables<double> &, int, double *,
+                                           int, const Flags *, int, hipStream_t);
+template void launch_green_inverse<float>(xfft_problem *, Work<float> &, const Tables<float> &, int, float *, int,
+                                          const Flags *, int, hipStream_t);
+
+}  // namespace xfft

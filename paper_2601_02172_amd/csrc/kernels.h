@@ -1,0 +1,54 @@
+// Kernel launchers of the X-FFT GPU library (internal).
+#pragma once
+
+#include "common.h"
+
+namespace xfft {
+
+SlotLayout slot_layout(const Geometry &g);
+int green_slots(const Geometry &g);
+
+// Operator r(x) = A x + (macro-strain term) on up to nrhs right-hand sides.
+// x/xe may be null (zero input).  sign multiplies the outputs.  When flags is
+// non-null a right-hand side r is skipped unless flags[r].active[parity].
+// Partial sums: dot (y . x) and the stress integral go to the operator slots.
+template <typename T>
+void launch_operator(xfft_problem *p, Work<T> &w, const Tables<T> &tb, const T *x, const T *xe, T *y, T *ye,
+                     bool use_ebar, T sign, int nrhs, const Flags *flags, int parity, double *vstress,
+                     hipStream_t s);
+
+// Green operator passes.  mode_x_fwd: the residual update f -= alpha z is fused
+// when z is non-null.  The z pass writes the Parseval partials.
+template <typename T>
+void launch_green_forward(xfft_problem *p, Work<T> &w, const Tables<T> &tb, T *f, const T *z, int nrhs,
+                          const Flags *flags, int parity, hipStream_t s);
+
+// mode 0: out = P^-1 f (FE part) written to `out`; mode 1: CG update
+// (u += alpha d_old, d = y + beta d_old); mode 2: d = y.
+template <typename T>
+void launch_green_inverse(xfft_problem *p, Work<T> &w, const Tables<T> &tb, int mode, T *out, int nrhs,
+                          const Flags *flags, int parity, hipStream_t s);
+
+// Enriched block: mode 0 residual partial only (out = f~ written when out non-null);
+// mode 1: f~ -= alpha z~ then partial.
+template <typename T>
+void launch_enr_update(xfft_problem *p, Work<T> &w, int mode, T *out, int nrhs, const Flags *flags, int parity,
+                       hipStream_t s);
+// mode 1: u~ += alpha d~, d~ = f~ + beta d~;  mode 2: d~ = f~
+template <typename T>
+void launch_enr_final(xfft_problem *p, Work<T> &w, int mode, int nrhs, const Flags *flags, int parity,
+                      hipStream_t s);
+
+// Scalar recurrences (one block per right-hand side).
+enum ScalarOp { SC_INIT_SIGMA = 0, SC_INIT_RES = 1, SC_ALPHA = 2, SC_BETA = 3, SC_SUM_ONLY = 4, SC_SUM_GREEN = 5 };
+void launch_scalars(xfft_problem *p, int op, int crit, int nrhs, int parity, double *sum_out, hipStream_t s);
+
+// Vector helpers for iterative refinement.
+void launch_round_to_float(xfft_problem *p, int nrhs, hipStream_t s);       // w32.f/fe <- w64.f/fe, w32.u/ue <- 0
+void launch_accumulate_correction(xfft_problem *p, int nrhs, hipStream_t s); // w64.u/ue += w32.u/ue
+
+// Setup.
+int run_setup(xfft_problem *p, const double *L_dev_raw);
+int compute_tables(xfft_problem *p);
+
+}  // namespace xfft

@@ -1,0 +1,493 @@
+// Matrix-free scaled X-FEM operator (eqs. linearSystem_element, resVector).
+//
+// Three kernels per application, all deterministic (no atomics):
+//  k_irregular  one thread per irregular voxel (a voxel with a cut element or
+//               elements of different materials); evaluates its six elements
+//               (cut ones by the per-side moment form of element.h) and writes
+//               the eight corner forces (3 FE + 3 scaled enriched) to a buffer;
+//  k_regular    z-marching LDS tile over the whole grid: every thread owns a
+//               column of voxels, evaluates the six Kuhn elements of one voxel
+//               per plane (or takes the buffered corner forces of an irregular
+//               voxel) and the corner forces are summed per node through LDS;
+//  k_enriched   one thread per enriched node; sums the buffered enriched
+//               corner forces of its (at most eight) irregular voxels.
+#include "kernels.h"
+#include "element.h"
+
+namespace xfft {
+
+namespace {
+
+constexpr int TE = 16;          // tile edge in threads
+constexpr int TO = TE - 1;      // owned nodes per tile edge
+constexpr int TC = TE + 1;      // node columns per tile edge (halo on the + side)
+
+__device__ __forceinline__ int wrapi(int a, int n) { return a < 0 ? a + n : (a >= n ? a - n : a); }
+
+template <typename T>
+struct OpArgs {
+    const T *x, *xe;
+    T *y, *ye;
+    const double *ebar;       // [rhs][6] Mandel
+    T sign;
+    const Flags *flags;
+    int parity;
+    const int32_t *vmat, *irr, *irr_j, *irr_lab, *jlist;
+    const T *irr_L, *d0is, *lame;
+    T *cutbuf;
+    double *partial;
+    int nslots, slot0;
+    double *vstress;          // [rhs][6][N] voxel-average Mandel stress, or null
+    int n0, n1, n2;
+    int64_t N, nX, nirr;
+    int kz, tiles_x;
+};
+
+template <typename T>
+__device__ __forceinline__ bool rhs_active(const OpArgs<T> &A, int r) {
+    return A.flags == nullptr || A.flags[r].active[A.parity] != 0;
+}
+
+template <typename T>
+__device__ __forceinline__ Sym<T> load_ebar(const double *e) {
+    T m[6];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) m[q] = (T)e[q];
+    return from_mandel<T>(m);
+}
+
+template <typename T>
+__device__ __forceinline__ void add_sym(double (&acc)[7], const Sym<T> &s) {
+    acc[1] += (double)s.xx; acc[2] += (double)s.yy; acc[3] += (double)s.zz;
+    acc[4] += (double)s.yz; acc[5] += (double)s.xz; acc[6] += (double)s.xy;
+}
+
+template <typename T>
+__device__ __forceinline__ void store_vstress(double *vs, int64_t N, int64_t v, const Sym<T> &s) {
+    const double r2 = 1.41421356237309504880;
+    vs[0 * N + v] = (double)s.xx; vs[1 * N + v] = (double)s.yy; vs[2 * N + v] = (double)s.zz;
+    vs[3 * N + v] = r2 * (double)s.yz; vs[4 * N + v] = r2 * (double)s.xz; vs[5 * N + v] = r2 * (double)s.xy;
+}
+
+// ---------------------------------------------------------------- regular voxel: 6 Kuhn tets
+template <int t, typename T, bool EB>
+__device__ __forceinline__ void regular_tet(const T (&U)[8][3], const Sym<T> &eb, T lamV, T mu2V, T (&F)[8][3],
+                                            Sym<T> &S) {
+    T v[4][3];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int i = 0; i < 3; ++i) v[a][i] = U[tet_corner(t, a)][i];
+    Sym<T> e = sym_of(kuhn_grad<t>(v));
+    if constexpr (EB) {
+        e.xx += eb.xx; e.yy += eb.yy; e.zz += eb.zz; e.yz += eb.yz; e.xz += eb.xz; e.xy += eb.xy;
+    }
+    const Sym<T> s = hooke(e, lamV, mu2V);
+    kuhn_scatter<t>(s, F);
+    sym_axpy(S, (T)1, s);
+}
+
+template <typename T, bool EB>
+__device__ __forceinline__ void regular_voxel(const T (&U)[8][3], const Sym<T> &eb, T lamV, T mu2V, T (&F)[8][3],
+                                              Sym<T> &S) {
+    regular_tet<0, T, EB>(U, eb, lamV, mu2V, F, S);
+    regular_tet<1, T, EB>(U, eb, lamV, mu2V, F, S);
+    regular_tet<2, T, EB>(U, eb, lamV, mu2V, F, S);
+    regular_tet<3, T, EB>(U, eb, lamV, mu2V, F, S);
+    regular_tet<4, T, EB>(U, eb, lamV, mu2V, F, S);
+    regular_tet<5, T, EB>(U, eb, lamV, mu2V, F, S);
+}
+
+// z-marching tile kernel.  Block = 16 x 16 threads; thread (tx, ty) evaluates the
+// voxel column with base (i0 - 1 + tx, j0 - 1 + ty) and owns the node column
+// with the same base when tx, ty >= 1.  Node (a, b) collects corner c of the
+// voxels (a - dx, b - dy): corners 0/4 from its own voxel, 1/5 from the thread
+// at tx - 1, 2/6 from ty - 1 and 3/7 from (tx - 1, ty - 1).
+template <typename T, bool HX, bool EB>
+__global__ __launch_bounds__(256) void k_regular(OpArgs<T> A) {
+    __shared__ T Dp[3][TC * TC][3];
+    __shared__ T FB[TE * TE][18];
+    __shared__ double red[4 * 7];
+
+    const int r = blockIdx.z;
+    if (!rhs_active(A, r)) return;
+    const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+    const int bx = blockIdx.x % A.tiles_x, by = blockIdx.x / A.tiles_x;
+    const int i0 = bx * TO, j0 = by * TO;
+    const int k0 = blockIdx.y * A.kz, k1 = min(k0 + A.kz, A.n2);
+    const int n0 = A.n0, n1 = A.n1, n2 = A.n2;
+    const int64_t N = A.N;
+    const int a = i0 - 1 + tx, b = j0 - 1 + ty;
+    // tiles may wrap more than once around small grids: full modulo here, once
+    const int aw = ((a % n0) + n0) % n0, bw = ((b % n1) + n1) % n1;
+    int64_t colxy[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+        const int col = tid + 256 * u;
+        const int cx = col % TC, cy = col / TC;
+        const int xi = (((i0 - 1 + cx) % n0) + n0) % n0, yi = (((j0 - 1 + cy) % n1) + n1) % n1;
+        colxy[u] = xi + (int64_t)n0 * yi;
+    }
+    const bool owner = tx >= 1 && ty >= 1 && a < n0 && b < n1;
+
+    const T *x = HX ? A.x + (int64_t)r * 3 * N : nullptr;
+    T *y = A.y + (int64_t)r * 3 * N;
+    const T *cutbuf = A.cutbuf + (int64_t)r * A.nirr * 48;
+    Sym<T> eb = sym_zero<T>();
+    if constexpr (EB) eb = load_ebar<T>(A.ebar + 6 * r);
+    double acc7[7] = {0, 0, 0, 0, 0, 0, 0};
+    double *vs = A.vstress ? A.vstress + (int64_t)r * 6 * N : nullptr;
+
+    auto load_plane = [&](int slot, int kk) {
+        if constexpr (HX) {
+            const int kw = wrapi(kk, n2);
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const int col = tid + 256 * u;
+                if (col < TC * TC) {
+                    const int64_t node = colxy[u] + (int64_t)n0 * n1 * kw;
+                    Dp[slot][col][0] = x[node];
+                    Dp[slot][col][1] = x[N + node];
+                    Dp[slot][col][2] = x[2 * N + node];
+                }
+            }
+        }
+    };
+
+    load_plane(0, k0 - 1);
+    load_plane(1, k0);
+    __syncthreads();
+
+    T acc[3] = {0, 0, 0};
+    for (int s = 0, kl = k0 - 1; kl < k1; ++s, ++kl) {
+        const int sb = s % 3, st = (s + 1) % 3;
+        if (kl + 2 <= k1) load_plane((s + 2) % 3, kl + 2);
+        const int kw = wrapi(kl, n2);
+        const int64_t vox = aw + (int64_t)n0 * (bw + (int64_t)n1 * kw);
+        const int m = A.vmat[vox];
+        T F[8][3];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) F[c][0] = F[c][1] = F[c][2] = (T)0;
+        if (m >= 0) {
+            T U[8][3];
+#pragma unroll
+            for (int c = 0; c < 8; ++c) {
+                const int col = (tx + (c & 1)) + TC * (ty + ((c >> 1) & 1));
+                const int sl = (c & 4) ? st : sb;
+#pragma unroll
+                for (int i = 0; i < 3; ++i) U[c][i] = HX ? Dp[sl][col][i] : (T)0;
+            }
+            const T V = (T)(1.0 / 6.0);
+            const T lamV = V * A.lame[2 * m], mu2V = V * (T)2 * A.lame[2 * m + 1];
+            Sym<T> S = sym_zero<T>();
+            regular_voxel<T, EB>(U, eb, lamV, mu2V, F, S);
+            if (owner && kl >= k0) {
+                add_sym(acc7, S);
+                if (vs) store_vstress(vs, N, vox, S);
+            }
+        } else {
+            const T *cb = cutbuf + (int64_t)(-m - 1) * 48;
+#pragma unroll
+            for (int c = 0; c < 8; ++c)
+#pragma unroll
+                for (int i = 0; i < 3; ++i) F[c][i] = cb[6 * c + i];
+        }
+        // publish the corners that belong to other threads' nodes
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            FB[tid][0 + i] = F[1][i];
+            FB[tid][3 + i] = F[2][i];
+            FB[tid][6 + i] = F[3][i];
+            FB[tid][9 + i] = F[5][i];
+            FB[tid][12 + i] = F[6][i];
+            FB[tid][15 + i] = F[7][i];
+        }
+        __syncthreads();
+        if (owner) {
+            T bot[3], top[3];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                bot[i] = F[0][i] + FB[tid - 1][0 + i] + FB[tid - 16][3 + i] + FB[tid - 17][6 + i];
+                top[i] = F[4][i] + FB[tid - 1][9 + i] + FB[tid - 16][12 + i] + FB[tid - 17][15 + i];
+            }
+            if (kl >= k0) {
+                const int64_t node = vox;
+                double dot = 0.0;
+#pragma unroll
+                for (int i = 0; i < 3; ++i) {
+                    const T out = A.sign * (acc[i] + bot[i]);
+                    y[i * N + node] = out;
+                    if constexpr (HX) dot += (double)out * (double)Dp[sb][tx + TC * ty][i];
+                }
+                acc7[0] += dot;
+            }
+#pragma unroll
+            for (int i = 0; i < 3; ++i) acc[i] = top[i];
+        }
+        __syncthreads();
+    }
+    block_sum<7>(acc7, red);
+    if (tid == 0) {
+        const int blk = blockIdx.x + gridDim.x * blockIdx.y;
+        double *P = A.partial + ((int64_t)r * A.nslots + A.slot0 + blk) * NPART;
+#pragma unroll
+        for (int q = 0; q < 7; ++q) P[q] = acc7[q];
+    }
+}
+
+// ---------------------------------------------------------------- irregular voxel
+template <int t, typename T, bool EB>
+__device__ __forceinline__ void irregular_tet(const T (&Lc)[8], const T (&U)[8][3], const T (&Q)[8][3],
+                                              const int32_t *lab, const T *lame, const Sym<T> &eb,
+                                              T (&F)[8][3], T (&Fe)[8][3], Sym<T> &S) {
+    constexpr int p0 = perm_axis(t, 0), p1 = perm_axis(t, 1), p2 = perm_axis(t, 2);
+    T L[4], u[4][3], q[4][3];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        L[a] = Lc[tet_corner(t, a)];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) { u[a][i] = U[tet_corner(t, a)][i]; q[a][i] = Q[tet_corner(t, a)][i]; }
+    }
+    const bool anyp = L[0] > (T)0 || L[1] > (T)0 || L[2] > (T)0 || L[3] > (T)0;
+    const bool anyn = L[0] < (T)0 || L[1] < (T)0 || L[2] < (T)0 || L[3] < (T)0;
+    const T V = (T)(1.0 / 6.0);
+    const Grad<T> HF = kuhn_grad<t>(u);
+    if (!(anyp && anyn)) {
+        const int m = lab[2 * t];
+        Sym<T> e = sym_of(HF);
+        if constexpr (EB) {
+            e.xx += eb.xx; e.yy += eb.yy; e.zz += eb.zz; e.yz += eb.yz; e.xz += eb.xz; e.xy += eb.xy;
+        }
+        const Sym<T> s = hooke(e, V * lame[2 * m], V * (T)2 * lame[2 * m + 1]);
+        kuhn_scatter<t>(s, F);
+        sym_axpy(S, (T)1, s);
+        return;
+    }
+    T Mp[4][4], Mm[4][4];
+    side_moments(L, V, Mp, Mm);
+    const Grad<T> Hq = kuhn_grad<t>(q);
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+        const T sg = side == 0 ? (T)1 : (T)-1;
+        const int m = lab[2 * t + side];
+        const T lam = lame[2 * m], mu2 = (T)2 * lame[2 * m + 1];
+        T w[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) w[a] = fabs(L[a]) - sg * L[a];
+        // G_s = sum_a w_a g_a with g0 = -e_p0, g1 = e_p0 - e_p1, g2 = e_p1 - e_p2, g3 = e_p2
+        T G[3];
+        G[p0] = w[1] - w[0];
+        G[p1] = w[2] - w[1];
+        G[p2] = w[3] - w[2];
+        Sym<T> Sh[4];
+#pragma unroll
+        for (int d = 0; d < 4; ++d) Sh[d] = sym_zero<T>();
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            Grad<T> K;
+#pragma unroll
+            for (int pp = 0; pp < 3; ++pp)
+#pragma unroll
+                for (int i = 0; i < 3; ++i) K.h[pp][i] = HF.h[pp][i] + w[c] * Hq.h[pp][i] + q[c][i] * G[pp];
+            Sym<T> e = sym_of(K);
+            if constexpr (EB) {
+                e.xx += eb.xx; e.yy += eb.yy; e.zz += eb.zz; e.yz += eb.yz; e.xz += eb.xz; e.xy += eb.xy;
+            }
+            const Sym<T> sc = hooke(e, lam, mu2);
+            const T *Mrow = side == 0 ? Mp[c] : Mm[c];
+#pragma unroll
+            for (int d = 0; d < 4; ++d) sym_axpy(Sh[d], Mrow[d], sc);
+        }
+        Sym<T> St = sym_zero<T>(), Sw = sym_zero<T>();
+#pragma unroll
+        for (int d = 0; d < 4; ++d) {
+            sym_axpy(St, (T)1, Sh[d]);
+            sym_axpy(Sw, w[d], Sh[d]);
+        }
+        kuhn_scatter<t>(St, F);
+        kuhn_scatter<t>(Sw, Fe);
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+            const int c = tet_corner(t, a);
+            const Sym<T> &s = Sh[a];
+            Fe[c][0] += s.xx * G[0] + s.xy * G[1] + s.xz * G[2];
+            Fe[c][1] += s.xy * G[0] + s.yy * G[1] + s.yz * G[2];
+            Fe[c][2] += s.xz * G[0] + s.yz * G[1] + s.zz * G[2];
+        }
+        sym_axpy(S, (T)1, St);
+    }
+}
+
+template <typename T, bool HX, bool EB>
+__global__ __launch_bounds__(128) void k_irregular(OpArgs<T> A) {
+    __shared__ double red[2 * 7];
+    const int r = blockIdx.y;
+    if (!rhs_active(A, r)) return;
+    const int64_t qv = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double acc7[7] = {0, 0, 0, 0, 0, 0, 0};
+    if (qv < A.nirr) {
+        const int64_t N = A.N;
+        const int64_t vox = A.irr[qv];
+        const int i = (int)(vox % A.n0), j = (int)((vox / A.n0) % A.n1), k = (int)(vox / ((int64_t)A.n0 * A.n1));
+        T Lc[8], U[8][3], Q[8][3], sc[8];
+        const T *x = HX ? A.x + (int64_t)r * 3 * N : nullptr;
+        const T *xe = HX ? A.xe + (int64_t)r * 3 * A.nX : nullptr;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            const int64_t node = wrapi(i + (c & 1), A.n0) +
+                                 (int64_t)A.n0 * (wrapi(j + ((c >> 1) & 1), A.n1) + (int64_t)A.n1 * wrapi(k + (c >> 2), A.n2));
+            Lc[c] = A.irr_L[qv * 8 + c];
+            const int jc = A.irr_j[qv * 8 + c];
+            sc[c] = jc >= 0 ? A.d0is[jc] : (T)0;
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                U[c][d] = HX ? x[d * N + node] : (T)0;
+                Q[c][d] = (HX && jc >= 0) ? sc[c] * xe[d * A.nX + jc] : (T)0;
+            }
+        }
+        Sym<T> eb = sym_zero<T>();
+        if constexpr (EB) eb = load_ebar<T>(A.ebar + 6 * r);
+        const int32_t *lab = A.irr_lab + qv * 12;
+        T F[8][3], Fe[8][3];
+#pragma unroll
+        for (int c = 0; c < 8; ++c)
+#pragma unroll
+            for (int d = 0; d < 3; ++d) F[c][d] = Fe[c][d] = (T)0;
+        Sym<T> S = sym_zero<T>();
+        irregular_tet<0, T, EB>(Lc, U, Q, lab, A.lame, eb, F, Fe, S);
+        irregular_tet<1, T, EB>(Lc, U, Q, lab, A.lame, eb, F, Fe, S);
+        irregular_tet<2, T, EB>(Lc, U, Q, lab, A.lame, eb, F, Fe, S);
+        irregular_tet<3, T, EB>(Lc, U, Q, lab, A.lame, eb, F, Fe, S);
+        irregular_tet<4, T, EB>(Lc, U, Q, lab, A.lame, eb, F, Fe, S);
+        irregular_tet<5, T, EB>(Lc, U, Q, lab, A.lame, eb, F, Fe, S);
+        T *cb = A.cutbuf + ((int64_t)r * A.nirr + qv) * 48;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            cb[6 * c + 0] = F[c][0];
+            cb[6 * c + 1] = F[c][1];
+            cb[6 * c + 2] = F[c][2];
+            cb[6 * c + 3] = sc[c] * Fe[c][0];
+            cb[6 * c + 4] = sc[c] * Fe[c][1];
+            cb[6 * c + 5] = sc[c] * Fe[c][2];
+        }
+        add_sym(acc7, S);
+        if (A.vstress) store_vstress(A.vstress + (int64_t)r * 6 * N, N, vox, S);
+    }
+    block_sum<7>(acc7, red);
+    if (threadIdx.x == 0) {
+        double *P = A.partial + ((int64_t)r * A.nslots + A.slot0 + blockIdx.x) * NPART;
+#pragma unroll
+        for (int q = 0; q < 7; ++q) P[q] = acc7[q];
+    }
+}
+
+// ---------------------------------------------------------------- enriched gather
+template <typename T, bool HX>
+__global__ __launch_bounds__(256) void k_enriched(OpArgs<T> A) {
+    __shared__ double red[4 * 7];
+    const int r = blockIdx.y;
+    if (!rhs_active(A, r)) return;
+    const int64_t jn = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double acc7[7] = {0, 0, 0, 0, 0, 0, 0};
+    if (jn < A.nX) {
+        const int64_t node = A.jlist[jn];
+        const int i = (int)(node % A.n0), j = (int)((node / A.n0) % A.n1), k = (int)(node / ((int64_t)A.n0 * A.n1));
+        const T *cutbuf = A.cutbuf + (int64_t)r * A.nirr * 48;
+        T s[3] = {0, 0, 0};
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            const int64_t vox = wrapi(i - (c & 1), A.n0) +
+                                (int64_t)A.n0 * (wrapi(j - ((c >> 1) & 1), A.n1) + (int64_t)A.n1 * wrapi(k - (c >> 2), A.n2));
+            const int m = A.vmat[vox];
+            if (m < 0) {
+                const T *cb = cutbuf + (int64_t)(-m - 1) * 48 + 6 * c + 3;
+                s[0] += cb[0]; s[1] += cb[1]; s[2] += cb[2];
+            }
+        }
+        T *ye = A.ye + (int64_t)r * 3 * A.nX;
+        const T *xe = HX ? A.xe + (int64_t)r * 3 * A.nX : nullptr;
+        double dot = 0.0;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const T out = A.sign * s[d];
+            ye[d * A.nX + jn] = out;
+            if constexpr (HX) dot += (double)out * (double)xe[d * A.nX + jn];
+        }
+        acc7[0] = dot;
+    }
+    block_sum<7>(acc7, red);
+    if (threadIdx.x == 0) {
+        double *P = A.partial + ((int64_t)r * A.nslots + A.slot0 + blockIdx.x) * NPART;
+#pragma unroll
+        for (int q = 0; q < 7; ++q) P[q] = acc7[q];
+    }
+}
+
+}  // namespace
+
+template <typename T>
+void launch_operator(xfft_problem *p, Work<T> &w, const Tables<T> &tb, const T *x, const T *xe, T *y, T *ye,
+                     bool use_ebar, T sign, int nrhs, const Flags *flags, int parity, double *vstress,
+                     hipStream_t s) {
+    const Geometry &g = p->g;
+    const SlotLayout &L = p->slots;
+    OpArgs<T> A;
+    A.x = x; A.xe = xe; A.y = y; A.ye = ye;
+    A.ebar = p->ebar; A.sign = sign; A.flags = flags; A.parity = parity;
+    A.vmat = p->vmat; A.irr = p->irr; A.irr_j = p->irr_j; A.irr_lab = p->irr_lab; A.jlist = p->jlist;
+    A.irr_L = tb.irr_L; A.d0is = tb.d0is; A.lame = tb.lame;
+    A.cutbuf = w.cutbuf; A.partial = p->partial; A.nslots = p->nslots;
+    A.vstress = vstress;
+    A.n0 = g.n0; A.n1 = g.n1; A.n2 = g.n2; A.N = g.N; A.nX = g.nX; A.nirr = g.nirr;
+    A.kz = L.kz; A.tiles_x = L.tiles_x;
+    const bool hx = x != nullptr;
+    if (g.nirr > 0) {
+        A.slot0 = L.cut0;
+        dim3 grid(L.cut_n, nrhs);
+        if (hx && use_ebar) k_irregular<T, true, true><<<grid, 128, 0, s>>>(A);
+        else if (hx) k_irregular<T, true, false><<<grid, 128, 0, s>>>(A);
+        else if (use_ebar) k_irregular<T, false, true><<<grid, 128, 0, s>>>(A);
+        else k_irregular<T, false, false><<<grid, 128, 0, s>>>(A);
+    }
+    {
+        A.slot0 = L.fe0;
+        dim3 grid(L.tiles_x * L.tiles_y, L.zchunks, nrhs);
+        if (hx && use_ebar) k_regular<T, true, true><<<grid, 256, 0, s>>>(A);
+        else if (hx) k_regular<T, true, false><<<grid, 256, 0, s>>>(A);
+        else if (use_ebar) k_regular<T, false, true><<<grid, 256, 0, s>>>(A);
+        else k_regular<T, false, false><<<grid, 256, 0, s>>>(A);
+    }
+    if (g.nX > 0) {
+        A.slot0 = L.enr0;
+        dim3 grid(L.enr_n, nrhs);
+        if (hx) k_enriched<T, true><<<grid, 256, 0, s>>>(A);
+        else k_enriched<T, false><<<grid, 256, 0, s>>>(A);
+    }
+}
+
+template void launch_operator<double>(xfft_problem *, Work<double> &, const Tables<double> &, const double *,
+                                      const double *, double *, double *, bool, double, int, const Flags *, int,
+                                      double *, hipStream_t);
+template void launch_operator<float>(xfft_problem *, Work<float> &, const Tables<float> &, const float *,
+                                     const float *, float *, float *, bool, float, int, const Flags *, int, double *,
+                                     hipStream_t);
+
+SlotLayout slot_layout(const Geometry &g) {
+    SlotLayout L{};
+    L.tiles_x = (g.n0 + TO - 1) / TO;
+    L.tiles_y = (g.n1 + TO - 1) / TO;
+    // planes per block: keep at least ~2048 blocks per right-hand side when possible
+    int kz = 16;
+    while (kz > 4 && (int64_t)L.tiles_x * L.tiles_y * ((g.n2 + kz - 1) / kz) < 2048) kz /= 2;
+    L.kz = kz;
+    L.zchunks = (g.n2 + kz - 1) / kz;
+    int at = 0;
+    L.fe0 = at; L.fe_n = L.tiles_x * L.tiles_y * L.zchunks; at += L.fe_n;
+    L.cut0 = at; L.cut_n = (int)((g.nirr + 127) / 128); at += L.cut_n;
+    L.enr0 = at; L.enr_n = (int)((g.nX + 255) / 256); at += L.enr_n;
+    L.grn0 = at; L.grn_n = 0; // filled by the FFT planner
+    L.total = at;
+    return L;
+}
+
+}  // namespace xfft

@@ -1,0 +1,90 @@
+"""Host-only checks of the C ABI: the library loads, exports every declared
+entry point, and rejects invalid input before touching a device."""
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2601_02172_amd as pkg
+from paper_2601_02172_amd import xfft as X
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "xfft.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(xfft_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_entry_point():
+    lib = X._lib()
+    names = _declared()
+    assert "xfft_setup" in names and "xfft_solve" in names
+    for name in names:
+        assert hasattr(lib, name), name
+    assert sorted(names) == sorted(X.EXPORTS)
+
+
+def test_default_options_and_strerror():
+    o = pkg.default_options()
+    assert o.rtol == 1e-10 and o.precision == X.XFFT_FP64 and o.snap_eps == 1e-6 and o.batch == 1
+    lib = X._lib()
+    for code in (0, 1, -1, -2, -3, -4):
+        assert len(lib.xfft_strerror(code)) > 0
+
+
+def _setup_rc(n, length, L, ph, lame):
+    lib = X._lib()
+    n = np.ascontiguousarray(n, dtype=np.int32)
+    length = np.ascontiguousarray(length, dtype=np.float64)
+    L = np.ascontiguousarray(L, dtype=np.float64)
+    ph = np.ascontiguousarray(ph, dtype=np.int32)
+    lame = np.ascontiguousarray(lame, dtype=np.float64)
+    h = ctypes.c_void_p()
+    rc = lib.xfft_setup(X._ip(n), X._dp(length), X._dp(L), X._ip(ph), lame.shape[0], X._dp(lame), None,
+                        ctypes.byref(h))
+    if rc == 0:
+        lib.xfft_destroy(h)
+    return rc
+
+
+@pytest.mark.parametrize("case", ["odd", "prime", "small", "noncubic", "nan", "phase", "mu", "bulk"])
+def test_setup_rejects_invalid_input(case):
+    n = [8, 8, 8]
+    length = [8.0, 8.0, 8.0]
+    N = 512
+    L = np.ones(N)
+    ph = np.zeros(N, dtype=np.int32)
+    lame = np.array([[1.0, 0.5]])
+    if case == "odd":
+        n = [9, 8, 8]
+        L = np.ones(576); ph = np.zeros(576, dtype=np.int32)
+    elif case == "prime":
+        n = [10, 8, 8]
+        L = np.ones(640); ph = np.zeros(640, dtype=np.int32)
+    elif case == "small":
+        n = [2, 8, 8]
+        L = np.ones(128); ph = np.zeros(128, dtype=np.int32)
+    elif case == "noncubic":
+        length = [8.0, 8.0, 9.0]
+    elif case == "nan":
+        L[17] = np.nan
+    elif case == "phase":
+        ph[3] = 1
+    elif case == "mu":
+        lame = np.array([[1.0, 0.0]])
+    elif case == "bulk":
+        lame = np.array([[-1.0, 0.5]])
+    assert _setup_rc(n, length, L, ph, lame) == X.XFFT_EINVAL
+
+
+def test_setup_without_device_reports_device_error():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    rc = _setup_rc([8, 8, 8], [8.0] * 3, np.ones(512), np.zeros(512, dtype=np.int32), np.array([[1.0, 0.5]]))
+    assert rc == X.XFFT_EDEVICE
