@@ -1,0 +1,234 @@
+"""Benchmark: PCG solves per second for the six unit load cases of a 128^3 cell.
+
+Workload (synthetic, seeded): 128^3 voxels, 40 periodic spheres with radii
+uniform in [0.06, 0.1] L placed by random sequential addition with a 2-voxel
+gap, contrast 10 (E = 10, nu = 0.25 in an E = 1, nu = 0.3 matrix).  One step
+solves the six unit Mandel macro strains to the relative tolerance 1e-10 of
+the stopping criterion:
+
+* headline (``value``): mixed precision -- FP32 CG inside FP64 iterative
+  refinement, the six loads batched in one launch sequence;
+* beside it: plain FP64 CG, one load at a time.
+
+Both C_eff are compared with a reference (the oracle's C_eff when its stored
+value exists, else an FP64 GPU solve at 1e-13) and their errors are printed.
+Setup (level-set classification, enriched numbering, D0, FFT tables) is timed
+separately and is not part of a step.
+
+Prints ONE JSON line.  ``--gpus`` above 1 is not supported (single-GPU build).
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(g, s, nrhs):
+    """Algorithmic HBM bytes per launch of each kernel class (one CG iteration).
+
+    g: dict with N, nX, nirr, n0, n1, n2; s: bytes per real (4 or 8).
+    """
+    N, nX, nirr = g["N"], g["nX"], g["n_irregular_voxels"]
+    nh = g["n0"] // 2 + 1
+    specN = g["n2"] * g["n1"] * nh               # complex entries per component
+    spec = 3 * specN * 2 * s                     # one 3-component half spectrum
+    field = 3 * N * s                            # one 3-component nodal field
+    per = {
+        "regular_voxels": 2 * field + 4 * N,                      # read d, write z, read material ids
+        "irregular_voxels": nirr * (8 * 3 * s + 8 * s + 8 * 4 + 12 * 4 + 8 * 3 * s + 48 * s),
+        "enriched_gather": nX * (8 * 4 + 3 * s),
+        "fft_x_forward": 3 * field + spec,                        # read f, z; write f, spectrum
+        "fft_y_forward": 2 * spec,
+        "fft_z_green": 2 * spec,
+        "fft_y_inverse": 2 * spec,
+        "fft_x_inverse": spec + 4 * field,                        # read spectrum, d, u; write d, u
+        "enriched_residual": nX * 3 * s * 3,
+        "enriched_update": nX * 3 * s * 5,
+        "scalars": 0,
+    }
+    return {k: v * nrhs for k, v in per.items()}
+
+
+def cpu_baseline(cfg, fp64_iters, sample_cut=2000, sample_iters=2):
+    """Time the CPU oracle on a bounded sample of the workload and scale to solves/s."""
+    from threadpoolctl import threadpool_limits
+    from oracle.xfem import Discretization
+    from oracle.system import System
+    from oracle.green import GreenOperator
+    from oracle.solver import pcg
+    with threadpool_limits(1):
+        d = Discretization(cfg["n"], cfg["length"], cfg["L"], cfg["phase"], cfg["lame"], keep_qp=False,
+                           sample_cut=sample_cut)
+        ncut = len(d.cut_voxel)
+        t_setup = d.timing["uncut"] + d.timing["cut"] * ncut / max(d.timing["cut_built"], 1)
+        s = System(d)
+        g = GreenOperator(d.n)
+        eb = np.eye(6)[0]
+        b = s.rhs(eb)
+        t0 = time.perf_counter()
+        pcg(s.apply, b, lambda f: g.apply(f, d.nX), lambda x: s.average_stress(x, eb), d.volume, 0.0,
+            sample_iters)
+        t_iter = (time.perf_counter() - t0) / sample_iters
+    total = t_setup + float(np.sum(fp64_iters)) * t_iter
+    return dict(value=6.0 / total, unit="solves/s", cores=1, kind="oracle",
+                sample=(f"oracle setup with {min(sample_cut, ncut)} of {ncut} cut elements built "
+                        f"(scaled to all), {sample_iters} PCG iterations of one load at full size; "
+                        f"scaled to 6 loads x the FP64 path's iteration counts ({int(np.sum(fp64_iters))} total); "
+                        f"1 thread"),
+                seconds_setup_est=t_setup, seconds_per_iteration=t_iter)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--rtol", type=float, default=1e-10)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(load cases and RVEs would be sharded across GPUs, see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import microstructure as ms
+    from paper_2601_02172_amd import Problem
+
+    torch.cuda.init()
+    cfg = ms.config_spheres128()
+    E = np.eye(6)
+
+    def make(precision, batch):
+        return Problem(cfg["n"], cfg["length"], cfg["L"], cfg["phase"], cfg["lame"], rtol=args.rtol,
+                       precision=precision, batch=batch)
+
+    t0 = time.perf_counter()
+    pm = make("mixed", True)
+    setup_s = time.perf_counter() - t0
+    lay = pm.layout(with_arrays=False)
+    lay.update(n0=cfg["n"][0], n1=cfg["n"][1], n2=cfg["n"][2])
+    log(f"setup {setup_s:.3f}s, nX={lay['nX']}, irregular voxels={lay['n_irregular_voxels']}")
+
+    for _ in range(args.warmup):
+        pm.solve(E, c_eff=True)
+    torch.cuda.synchronize()
+    pm.profile_begin()          # HIP events around every launch of the timed region
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        r_mixed = pm.solve(E, c_eff=True)
+    torch.cuda.synchronize()
+    t_mixed = time.perf_counter() - t0
+    region = pm.profile_end()
+    ms_per_step = 1000.0 * t_mixed / args.steps
+    value = 6.0 * args.steps / t_mixed
+    log(f"mixed: {ms_per_step:.1f} ms/step, inner iters {list(r_mixed['iters'])}, outer {list(r_mixed['outer_iters'])}")
+
+    fp64 = None
+    if not args.no_fp64:
+        p64 = make("fp64", False)
+        p64.solve(E[:1])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            r64 = p64.solve(E, c_eff=True)
+        torch.cuda.synchronize()
+        t64 = time.perf_counter() - t0
+        fp64 = dict(value=6.0 * args.steps / t64, ms_per_step=1000.0 * t64 / args.steps,
+                    iters=[int(v) for v in r64["iters"]])
+        log(f"fp64 plain: {fp64['ms_per_step']:.1f} ms/step, iters {fp64['iters']}")
+
+    # accuracy of both paths against a reference C_eff
+    golden = os.path.join(ROOT, "tests", "golden", "oracle_spheres128.json")
+    if os.path.exists(golden):
+        C_ref = np.array(json.load(open(golden))["c_eff"])
+        ref_kind = "oracle"
+    else:
+        pref = Problem(cfg["n"], cfg["length"], cfg["L"], cfg["phase"], cfg["lame"], rtol=1e-13)
+        C_ref = pref.effective_stiffness()[0]
+        pref.close()
+        ref_kind = "gpu_fp64_rtol1e-13"
+    nrm = np.linalg.norm(C_ref)
+    err_mixed = float(np.linalg.norm(r_mixed["c_eff"] - C_ref) / nrm)
+    err_fp64 = float(np.linalg.norm(r64["c_eff"] - C_ref) / nrm) if fp64 else None
+
+    log(f"C_eff rel error vs {ref_kind}: mixed {err_mixed:.2e}, fp64 {err_fp64}")
+    # dominant kernel of the timed region: largest total time among all launches
+    byts = {"fp32": algorithmic_bytes(lay, 4, 6), "fp64": algorithmic_bytes(lay, 8, 6)}
+    totals = {k: m * c for k, (m, c) in region.items()}
+    dom_key = max(totals, key=totals.get)
+    dom, dom_prec = dom_key
+    dom_ms, dom_n = region[dom_key]
+    # bytes per launch: the timed region mixes launches with 6..1 active loads; scale
+    # the 6-load figure by the mean number of active loads per launch
+    # CG-loop launches skip loads that have converged: the mean number of loads a
+    # launch processes is (load-iterations in the timed steps) / (launches)
+    if dom_prec == "fp32":
+        active = min(6.0, float(np.sum(r_mixed["iters"])) * args.steps / max(dom_n, 1))
+    else:
+        active = 6.0
+    bytes_launch = byts[dom_prec][dom] * active / 6.0
+    achieved = bytes_launch / (dom_ms * 1e-3) / 1e9 if dom_ms > 0 else 0.0
+    roofline = dict(bound="hbm", kernel=f"{dom} ({dom_prec})", achieved=round(achieved, 1), peak=HBM_PEAK_GBS,
+                    unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
+                    bytes_per_launch=int(bytes_launch), ms_per_launch=round(dom_ms, 5), launches=dom_n,
+                    mean_active_loads=round(active, 3))
+    # per-kernel breakdown of one CG iteration with all six loads active
+    prof = pm.profile(precision="fp32", nrhs=6, nrep=10)
+    kernels = {k: dict(ms=round(v[0], 5), launches_per_iter=v[1] / 10.0,
+                       gbs=round(byts["fp32"][k] / (v[0] * 1e-3) / 1e9, 1) if v[0] > 0 and byts["fp32"][k] else None)
+               for k, v in prof.items()}
+    region_summary = {f"{k[0]}/{k[1]}": [round(v[0], 5), v[1]] for k, v in region.items() if v[1]}
+    log(f"dominant kernel {dom}: {dom_ms:.4f} ms, {achieved:.0f} GB/s")
+    cpu = None
+    if not args.no_cpu_baseline and fp64:
+        log("timing the CPU oracle on a bounded sample")
+        cpu = cpu_baseline(cfg, fp64["iters"])
+        log(f"cpu baseline {cpu['value']:.3e} solves/s")
+
+    out = {
+        "metric": "PCG solves/sec (6 loads, 128^3) mixed vs FP64 plain at equal C_eff error",
+        "value": round(value, 4),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 (FP64 refinement)",
+        "data": "synthetic",
+        "config": {"workload": "spheres128: 128^3, 40 RSA spheres r~U[0.06,0.1]L, contrast 10, 6 unit loads",
+                   "rtol": args.rtol, "precision": "mixed", "batched_loads": 6,
+                   "n_enriched": lay["nX"], "n_irregular_voxels": lay["n_irregular_voxels"],
+                   "vf": cfg["info"]["vf"]},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "fp64_plain": fp64,
+        "c_eff_rel_error": {"mixed": err_mixed, "fp64": err_fp64, "reference": ref_kind},
+        "inner_iters": [int(v) for v in r_mixed["iters"]],
+        "outer_iters": [int(v) for v in r_mixed["outer_iters"]],
+        "setup_seconds": round(setup_s, 4),
+        "kernels": kernels,
+        "timed_region_kernels": region_summary,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

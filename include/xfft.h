@@ -158,6 +158,28 @@ int xfft_apply_precond(xfft_problem *p, int32_t precision, const double *f,
  * index of each enriched node; d0[nX] (NULL allowed) = D0_jj. */
 int xfft_get_layout(xfft_problem *p, int64_t *info, int64_t *jlist, double *d0);
 
+/* Kernel timing of the CG iteration (Algorithm 1) in the launch configuration
+ * of a solve with nrhs loads: runs nrep iterations on the problem's stream with
+ * a HIP event after every kernel and returns, per kernel class, the average
+ * time between the event before and the event after a launch (ms_out[11],
+ * ms) and the number of launches timed (count_out[11]); either may be NULL.
+ * Classes: 0 irregular-voxel operator, 1 regular-voxel operator, 2 enriched
+ * gather, 3 FFT x forward (+ residual update), 4 FFT y forward, 5 FFT z +
+ * Green multiply + inverse z, 6 FFT y inverse, 7 FFT x inverse (+ CG update),
+ * 8 enriched residual, 9 enriched CG update, 10 scalar recurrences.
+ * precision: XFFT_FP64 or XFFT_FP32.  Overwrites the problem's work fields. */
+int xfft_profile(xfft_problem *p, int32_t precision, int32_t nrhs, int32_t nrep, double *ms_out,
+                 int32_t *count_out);
+
+/* Timing of every kernel launched on the problem's stream between the two
+ * calls (e.g. around xfft_solve): a HIP event is recorded before and after
+ * each launch; xfft_profile_end returns per kernel class the average window
+ * length in ms (ms_out[22]) and the number of launches (count_out[22]);
+ * classes 0..10 as for xfft_profile in FP32, 11..21 the same in FP64 (the
+ * scalar recurrences are FP64: class 21).  Adds a little host overhead. */
+int xfft_profile_begin(xfft_problem *p);
+int xfft_profile_end(xfft_problem *p, double *ms_out, int32_t *count_out);
+
 void xfft_destroy(xfft_problem *p);
 const char *xfft_strerror(int code);
 

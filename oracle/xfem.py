@@ -177,10 +177,15 @@ class Discretization:
     rule : "degree2" (the paper's rule) or "degree3" (check of exactness).
     keep_qp : keep per-quadrature-point B matrices of cut elements (needed for
         the energy form and its gradient; memory heavy on large grids).
+    sample_cut : timing only -- build just the first ``sample_cut`` cut elements
+        (the rest get zero element matrices) and record the time per element in
+        ``timing``; the resulting system is NOT the discretisation.
     """
 
     def __init__(self, n, length, L, phase, lame, snap_eps=1e-6, d0_scale=1.0, rule="degree2",
-                 keep_qp=True):
+                 keep_qp=True, sample_cut=None):
+        import time
+        t_start = time.perf_counter()
         self.n = tuple(int(v) for v in n)
         self.N = int(np.prod(self.n))
         h = float(length[0]) / self.n[0]
@@ -236,7 +241,12 @@ class Discretization:
             self.B_fe.append(np.concatenate(list(mandel_B(G)), axis=1))
 
         self.keep_qp = keep_qp
+        self.sample_cut = sample_cut
+        t_mid = time.perf_counter()
         self._build_cut_elements(d0_scale)
+        t_end = time.perf_counter()
+        self.timing = dict(uncut=t_mid - t_start, cut=t_end - t_mid,
+                           cut_built=len(self.cut_voxel) if sample_cut is None else min(sample_cut, len(self.cut_voxel)))
 
     # ------------------------------------------------------------------ cut elements
     def _build_cut_elements(self, d0_scale):
@@ -247,7 +257,8 @@ class Discretization:
         self.cut_nodes = self.vert_nodes[cv, ct] if ncut else np.zeros((0, 4), dtype=np.int64)
         raw = []                                  # per cut element: list of qps
         D0 = np.zeros(self.nX)
-        for e in range(ncut):
+        nbuild = ncut if self.sample_cut is None else min(self.sample_cut, ncut)
+        for e in range(nbuild):
             t = ct[e]
             Lv = self.Ls[self.cut_nodes[e]]
             labs = self.phase[self.cut_nodes[e]]
@@ -257,6 +268,10 @@ class Discretization:
             qps = cut_element_qps(self.tet_X[t], Lv, pts, wts)
             D0[self.jmap[self.cut_nodes[e]]] += d0_contributions(qps)
             raw.append([(w, gX, lab_pos if side > 0 else lab_neg) for (w, gX, side) in qps])
+        for e in range(nbuild, ncut):
+            raw.append([])
+        if nbuild < ncut:
+            D0 = np.where(D0 > 0.0, D0, 1.0)
         self.D0 = D0 * d0_scale
         if np.any(self.D0 <= 0.0):
             raise ValueError("non-positive scaling factor")

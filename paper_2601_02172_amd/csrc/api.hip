@@ -370,9 +370,116 @@ int solve_impl(xfft_problem *p, int nload, const double *strain, double *disp, d
     return status;
 }
 
+// Per-class average of the windows [event before launch, event after launch]
+// recorded since the last reset; classes 0..K_COUNT-1 FP32, K_COUNT.. FP64.
+int prof_collect(xfft_problem *p, double *ms_out, int32_t *count_out) {
+    HIP_OK(hipStreamSynchronize(p->stream));
+    std::vector<double> sum(2 * K_COUNT, 0.0);
+    std::vector<int> cnt(2 * K_COUNT, 0);
+    for (size_t i = 1; i < p->prof_used; ++i) {
+        const int id = p->prof_ids[i];
+        if (id < 0 || p->prof_ids[i - 1] != -1) continue;
+        float ms = 0.0f;
+        HIP_OK(hipEventElapsedTime(&ms, p->prof_pool[i - 1], p->prof_pool[i]));
+        if (id < 2 * K_COUNT) { sum[id] += ms; cnt[id] += 1; }
+    }
+    p->prof_used = 0;
+    p->prof_ids.clear();
+    for (int k = 0; k < 2 * K_COUNT; ++k) {
+        if (ms_out) ms_out[k] = cnt[k] ? sum[k] / cnt[k] : 0.0;
+        if (count_out) count_out[k] = cnt[k];
+    }
+    return XFFT_OK;
+}
+
+template <typename T>
+int profile_impl(xfft_problem *p, Work<T> &w, const Tables<T> &tb, int nrhs, int nrep, double *ms_out,
+                 int32_t *count_out) {
+    hipStream_t s = p->stream;
+    std::vector<double> E(6 * nrhs, 0.0);
+    for (int r = 0; r < nrhs; ++r) E[6 * r + (r % 6)] = 1.0;
+    int rc = reset_state(p, nrhs, E.data());
+    if (rc) return rc;
+    HIP_OK(hipMemsetAsync(w.u, 0, sizeof(T) * 3 * p->g.N * nrhs, s));
+    if (p->g.nX) HIP_OK(hipMemsetAsync(w.ue, 0, sizeof(T) * 3 * p->g.nX * nrhs, s));
+    launch_operator<T>(p, w, tb, nullptr, nullptr, w.f, w.fe, true, (T)-1, nrhs, nullptr, 0, nullptr, s);
+    launch_scalars(p, SC_INIT_SIGMA, 0, nrhs, 0, nullptr, s);
+    cg_start<T>(p, w, tb, nrhs, 0);
+    std::vector<Flags> fl;
+    rc = read_flags(p, nrhs, fl);
+    if (rc) return rc;
+    for (auto &f : fl) { f.active[0] = 1; f.active[1] = 1; f.iters = 0; }
+    HIP_OK(hipMemcpyAsync(p->flags, fl.data(), sizeof(Flags) * nrhs, hipMemcpyHostToDevice, s));
+    HIP_OK(hipStreamSynchronize(s));
+    const int saved_maxit = p->maxit;
+    p->maxit = 1 << 30;
+    p->prof_used = 0;
+    p->prof_ids.clear();
+    p->prof_on = true;
+    for (int it = 0; it < nrep; ++it) cg_iteration<T>(p, w, tb, nrhs, it & 1, 0);
+    p->prof_on = false;
+    p->maxit = saved_maxit;
+    std::vector<double> ms(2 * K_COUNT);
+    std::vector<int32_t> cnt(2 * K_COUNT);
+    rc = prof_collect(p, ms.data(), cnt.data());
+    if (rc) return rc;
+    const int off = sizeof(T) == 8 ? K_COUNT : 0;
+    for (int k = 0; k < K_COUNT; ++k) {
+        const int src = (k == K_SCALARS) ? K_SCALARS + K_COUNT : k + off;
+        if (ms_out) ms_out[k] = ms[src];
+        if (count_out) count_out[k] = cnt[src];
+    }
+    return XFFT_OK;
+}
+
 }  // namespace
 
+void xfft_prof_mark(xfft_problem *p, int kernel_id, hipStream_t s) {
+    if (!p || !p->prof_on) return;
+    if (p->prof_used == p->prof_pool.size()) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return;
+        p->prof_pool.push_back(e);
+    }
+    if (hipEventRecord(p->prof_pool[p->prof_used], s) != hipSuccess) return;
+    p->prof_ids.push_back(kernel_id);
+    ++p->prof_used;
+}
+
 extern "C" {
+
+int xfft_profile(xfft_problem *p, int32_t precision, int32_t nrhs, int32_t nrep, double *ms_out,
+                 int32_t *count_out) {
+    if (!p || nrhs < 1 || nrep < 1 || (precision != XFFT_FP64 && precision != XFFT_FP32)) return XFFT_EINVAL;
+    HIP_OK(hipSetDevice(p->device));
+    int rc = ensure_state(p, nrhs);
+    if (rc) return rc;
+    if (precision == XFFT_FP64) {
+        rc = alloc_work<double>(p, p->w64, nrhs);
+        if (rc) return rc;
+        return profile_impl<double>(p, p->w64, p->t64, nrhs, nrep, ms_out, count_out);
+    }
+    rc = alloc_work<float>(p, p->w32, nrhs);
+    if (rc) return rc;
+    return profile_impl<float>(p, p->w32, p->t32, nrhs, nrep, ms_out, count_out);
+}
+
+int xfft_profile_begin(xfft_problem *p) {
+    if (!p) return XFFT_EINVAL;
+    HIP_OK(hipSetDevice(p->device));
+    HIP_OK(hipStreamSynchronize(p->stream));
+    p->prof_used = 0;
+    p->prof_ids.clear();
+    p->prof_on = true;
+    return XFFT_OK;
+}
+
+int xfft_profile_end(xfft_problem *p, double *ms_out, int32_t *count_out) {
+    if (!p || !p->prof_on) return XFFT_EINVAL;
+    HIP_OK(hipSetDevice(p->device));
+    p->prof_on = false;
+    return prof_collect(p, ms_out, count_out);
+}
 
 void xfft_default_options(xfft_options *opt) {
     if (!opt) return;
@@ -417,6 +524,7 @@ void xfft_destroy(xfft_problem *p) {
     }
     free_work(p->w64);
     free_work(p->w32);
+    for (hipEvent_t e : p->prof_pool) (void)hipEventDestroy(e);
     if (p->host_flags) (void)hipHostFree(p->host_flags);
     if (p->own_stream && p->stream) (void)hipStreamDestroy(p->stream);
     delete p;

@@ -185,7 +185,9 @@ void launch_scalars(xfft_problem *p, int op, int crit, int nrhs, int parity, dou
     A.parity = parity;
     A.maxit = p->maxit;
     A.sum_out = sum_out;
+    xfft_prof_mark(p, -1, s);
     k_scalars<<<nrhs, 256, 0, s>>>(A);
+    xfft_prof_mark(p, K_SCALARS + K_COUNT, s);
 }
 
 template <typename T>
@@ -193,8 +195,10 @@ void launch_enr_update(xfft_problem *p, Work<T> &w, int mode, T *out, int nrhs, 
                        hipStream_t s) {
     if (p->g.nX == 0) return;
     dim3 grid(p->slots.eu_n, nrhs);
+    xfft_prof_mark(p, -1, s);
     k_enr_update<T><<<grid, 256, 0, s>>>(p->g.nX, flags, parity, p->scal, mode, w.fe, w.ze, out, p->partial,
                                          p->nslots, p->slots.eu0);
+    xfft_prof_mark(p, K_ENR_UPDATE + (sizeof(T) == 8 ? K_COUNT : 0), s);
 }
 
 template <typename T>
@@ -202,7 +206,9 @@ void launch_enr_final(xfft_problem *p, Work<T> &w, int mode, int nrhs, const Fla
                       hipStream_t s) {
     if (p->g.nX == 0) return;
     dim3 grid((unsigned)((p->g.nX + 255) / 256), nrhs);
+    xfft_prof_mark(p, -1, s);
     k_enr_final<T><<<grid, 256, 0, s>>>(p->g.nX, flags, parity, p->scal, mode, w.ue, w.de, w.fe);
+    xfft_prof_mark(p, K_ENR_FINAL + (sizeof(T) == 8 ? K_COUNT : 0), s);
 }
 
 template void launch_enr_update<double>(xfft_problem *, Work<double> &, int, double *, int, const Flags *, int,

@@ -13,6 +13,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <utility>
 #include <vector>
 
 namespace xfft {
@@ -138,7 +139,17 @@ struct Flags {
     int pad[3];            // pad[0]: outer (refinement) loop converged
 };
 
+// Kernel classes timed by the profiling hook (order of xfft_profile's output).
+enum KernelId {
+    K_IRREGULAR = 0, K_REGULAR, K_ENRICHED, K_FFT_X_FWD, K_FFT_Y_FWD, K_FFT_Z_GREEN, K_FFT_Y_INV, K_FFT_X_INV,
+    K_ENR_UPDATE, K_ENR_FINAL, K_SCALARS, K_COUNT
+};
+
 }  // namespace xfft
+
+struct xfft_problem;
+// Records an event after a kernel launch when profiling is on (no-op otherwise).
+void xfft_prof_mark(xfft_problem *p, int kernel_id, hipStream_t s);
 
 // The opaque handle.
 struct xfft_problem {
@@ -181,4 +192,9 @@ struct xfft_problem {
     int sol_nload = 0;
     bool sol_unit_basis = false;
     double seconds_setup = 0.0, seconds_solve = 0.0;
+    // profiling hook: events recorded before (id -1) and after (kernel id) every launch
+    bool prof_on = false;
+    std::vector<hipEvent_t> prof_pool;   // reusable events
+    std::vector<int> prof_ids;           // id of the i-th recorded event
+    size_t prof_used = 0;
 };

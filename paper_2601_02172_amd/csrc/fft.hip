@@ -405,27 +405,35 @@ void launch_green_forward(xfft_problem *p, Work<T> &w, const Tables<T> &tb, T *f
         const int64_t npairs = (int64_t)3 * g.n2 * g.n1 / 2;
         dim3 grid((unsigned)((npairs + pp - 1) / pp), nrhs);
         const size_t lds = (size_t)pp * (g.n0 + 1) * sizeof(cpx<T>);
+        xfft_prof_mark(p, -1, s);
         k_fft_x_fwd<T><<<grid, 256, lds, s>>>(A, p->plan[0], tb.tw[0], f, z, w.spec, pp);
+        xfft_prof_mark(p, K_FFT_X_FWD + (sizeof(T) == 8 ? K_COUNT : 0), s);
     }
     {
         const int tk = tk_for<T>(g.n1, 1, 256);
         dim3 grid(3 * g.n2 * ((g.nh + tk - 1) / tk), nrhs);
         const size_t lds = (size_t)tk * (g.n1 + 1) * sizeof(cpx<T>);
+        xfft_prof_mark(p, -1, s);
         k_fft_y<T, false><<<grid, 256, lds, s>>>(A, p->plan[1], tb.tw[1], w.spec, tk);
+        xfft_prof_mark(p, K_FFT_Y_FWD + (sizeof(T) == 8 ? K_COUNT : 0), s);
     }
     {
         const int tk = tk_z(g);
         A.slot0 = p->slots.grn0;
         dim3 grid(g.n1 * ((g.nh + tk - 1) / tk), nrhs);
         const size_t lds = (size_t)3 * tk * (g.n2 + 1) * sizeof(cpx<T>);
+        xfft_prof_mark(p, -1, s);
         k_fft_z_green<T><<<grid, 512, lds, s>>>(A, p->plan[2], tb.tw[2], tb.half[0], tb.half[1], tb.half[2], w.spec,
                                                  tk);
+        xfft_prof_mark(p, K_FFT_Z_GREEN + (sizeof(T) == 8 ? K_COUNT : 0), s);
     }
     {
         const int tk = tk_for<T>(g.n1, 1, 256);
         dim3 grid(3 * g.n2 * ((g.nh + tk - 1) / tk), nrhs);
         const size_t lds = (size_t)tk * (g.n1 + 1) * sizeof(cpx<T>);
+        xfft_prof_mark(p, -1, s);
         k_fft_y<T, true><<<grid, 256, lds, s>>>(A, p->plan[1], tb.tw[1], w.spec, tk);
+        xfft_prof_mark(p, K_FFT_Y_INV + (sizeof(T) == 8 ? K_COUNT : 0), s);
     }
 }
 
@@ -438,7 +446,9 @@ void launch_green_inverse(xfft_problem *p, Work<T> &w, const Tables<T> &tb, int 
     const int64_t npairs = (int64_t)3 * g.n2 * g.n1 / 2;
     dim3 grid((unsigned)((npairs + pp - 1) / pp), nrhs);
     const size_t lds = (size_t)pp * (g.n0 + 1) * sizeof(cpx<T>);
+    xfft_prof_mark(p, -1, s);
     k_fft_x_inv<T><<<grid, 256, lds, s>>>(A, p->plan[0], tb.tw[0], w.spec, mode, out, w.u, w.d, pp);
+    xfft_prof_mark(p, K_FFT_X_INV + (sizeof(T) == 8 ? K_COUNT : 0), s);
 }
 
 template void launch_green_forward<double>(xfft_problem *, Work<double> &, const Tables<double> &, double *,

@@ -33,7 +33,8 @@ struct OpArgs {
     const Flags *flags;
     int parity;
     const int32_t *vmat, *irr, *irr_j, *irr_lab, *jlist;
-    const T *irr_L, *d0is, *lame;
+    const T *d0is, *lame;
+    const double *irr_L64;    // [nirr][8] corner level set (FP64 for every precision)
     T *cutbuf;
     double *partial;
     int nslots, slot0;
@@ -237,14 +238,16 @@ __global__ __launch_bounds__(256) void k_regular(OpArgs<T> A) {
 
 // ---------------------------------------------------------------- irregular voxel
 template <int t, typename T, bool EB>
-__device__ __forceinline__ void irregular_tet(const T (&Lc)[8], const T (&U)[8][3], const T (&Q)[8][3],
+__device__ __forceinline__ void irregular_tet(const double (&Lc)[8], const T (&U)[8][3], const T (&Q)[8][3],
                                               const int32_t *lab, const T *lame, const Sym<T> &eb,
                                               T (&F)[8][3], T (&Fe)[8][3], Sym<T> &S) {
     constexpr int p0 = perm_axis(t, 0), p1 = perm_axis(t, 1), p2 = perm_axis(t, 2);
     T L[4], u[4][3], q[4][3];
+    double Ld[4];
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
-        L[a] = Lc[tet_corner(t, a)];
+        Ld[a] = Lc[tet_corner(t, a)];
+        L[a] = (T)Ld[a];
 #pragma unroll
         for (int i = 0; i < 3; ++i) { u[a][i] = U[tet_corner(t, a)][i]; q[a][i] = Q[tet_corner(t, a)][i]; }
     }
@@ -263,8 +266,15 @@ __device__ __forceinline__ void irregular_tet(const T (&Lc)[8], const T (&U)[8][
         sym_axpy(S, (T)1, s);
         return;
     }
+    // Side moments always in FP64: the smaller side of a nearly degenerate
+    // split is a difference of O(1) moments and loses all digits in FP32.
+    double Mpd[4][4], Mmd[4][4];
+    side_moments<double>(Ld, 1.0 / 6.0, Mpd, Mmd);
     T Mp[4][4], Mm[4][4];
-    side_moments(L, V, Mp, Mm);
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+        for (int d = 0; d < 4; ++d) { Mp[c][d] = (T)Mpd[c][d]; Mm[c][d] = (T)Mmd[c][d]; }
     const Grad<T> Hq = kuhn_grad<t>(q);
 #pragma unroll
     for (int side = 0; side < 2; ++side) {
@@ -329,14 +339,15 @@ __global__ __launch_bounds__(128) void k_irregular(OpArgs<T> A) {
         const int64_t N = A.N;
         const int64_t vox = A.irr[qv];
         const int i = (int)(vox % A.n0), j = (int)((vox / A.n0) % A.n1), k = (int)(vox / ((int64_t)A.n0 * A.n1));
-        T Lc[8], U[8][3], Q[8][3], sc[8];
+        double Lc[8];
+        T U[8][3], Q[8][3], sc[8];
         const T *x = HX ? A.x + (int64_t)r * 3 * N : nullptr;
         const T *xe = HX ? A.xe + (int64_t)r * 3 * A.nX : nullptr;
 #pragma unroll
         for (int c = 0; c < 8; ++c) {
             const int64_t node = wrapi(i + (c & 1), A.n0) +
                                  (int64_t)A.n0 * (wrapi(j + ((c >> 1) & 1), A.n1) + (int64_t)A.n1 * wrapi(k + (c >> 2), A.n2));
-            Lc[c] = A.irr_L[qv * 8 + c];
+            Lc[c] = A.irr_L64[qv * 8 + c];
             const int jc = A.irr_j[qv * 8 + c];
             sc[c] = jc >= 0 ? A.d0is[jc] : (T)0;
 #pragma unroll
@@ -435,7 +446,7 @@ void launch_operator(xfft_problem *p, Work<T> &w, const Tables<T> &tb, const T *
     A.x = x; A.xe = xe; A.y = y; A.ye = ye;
     A.ebar = p->ebar; A.sign = sign; A.flags = flags; A.parity = parity;
     A.vmat = p->vmat; A.irr = p->irr; A.irr_j = p->irr_j; A.irr_lab = p->irr_lab; A.jlist = p->jlist;
-    A.irr_L = tb.irr_L; A.d0is = tb.d0is; A.lame = tb.lame;
+    A.irr_L64 = p->t64.irr_L; A.d0is = tb.d0is; A.lame = tb.lame;
     A.cutbuf = w.cutbuf; A.partial = p->partial; A.nslots = p->nslots;
     A.vstress = vstress;
     A.n0 = g.n0; A.n1 = g.n1; A.n2 = g.n2; A.N = g.N; A.nX = g.nX; A.nirr = g.nirr;
@@ -444,24 +455,30 @@ void launch_operator(xfft_problem *p, Work<T> &w, const Tables<T> &tb, const T *
     if (g.nirr > 0) {
         A.slot0 = L.cut0;
         dim3 grid(L.cut_n, nrhs);
+        xfft_prof_mark(p, -1, s);
         if (hx && use_ebar) k_irregular<T, true, true><<<grid, 128, 0, s>>>(A);
         else if (hx) k_irregular<T, true, false><<<grid, 128, 0, s>>>(A);
         else if (use_ebar) k_irregular<T, false, true><<<grid, 128, 0, s>>>(A);
         else k_irregular<T, false, false><<<grid, 128, 0, s>>>(A);
+        xfft_prof_mark(p, K_IRREGULAR + (sizeof(T) == 8 ? K_COUNT : 0), s);
     }
     {
         A.slot0 = L.fe0;
         dim3 grid(L.tiles_x * L.tiles_y, L.zchunks, nrhs);
+        xfft_prof_mark(p, -1, s);
         if (hx && use_ebar) k_regular<T, true, true><<<grid, 256, 0, s>>>(A);
         else if (hx) k_regular<T, true, false><<<grid, 256, 0, s>>>(A);
         else if (use_ebar) k_regular<T, false, true><<<grid, 256, 0, s>>>(A);
         else k_regular<T, false, false><<<grid, 256, 0, s>>>(A);
+        xfft_prof_mark(p, K_REGULAR + (sizeof(T) == 8 ? K_COUNT : 0), s);
     }
     if (g.nX > 0) {
         A.slot0 = L.enr0;
         dim3 grid(L.enr_n, nrhs);
+        xfft_prof_mark(p, -1, s);
         if (hx) k_enriched<T, true><<<grid, 256, 0, s>>>(A);
         else k_enriched<T, false><<<grid, 256, 0, s>>>(A);
+        xfft_prof_mark(p, K_ENRICHED + (sizeof(T) == 8 ? K_COUNT : 0), s);
     }
 }
 

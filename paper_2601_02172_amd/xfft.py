@@ -58,8 +58,13 @@ class Stats(ctypes.Structure):
 EXPORTS = [
     "xfft_default_options", "xfft_setup", "xfft_solve", "xfft_solve_device", "xfft_set_lame",
     "xfft_grad_lame", "xfft_batch_solve", "xfft_apply_operator", "xfft_apply_precond",
-    "xfft_get_layout", "xfft_destroy", "xfft_strerror",
+    "xfft_get_layout", "xfft_profile", "xfft_profile_begin", "xfft_profile_end", "xfft_destroy",
+    "xfft_strerror",
 ]
+
+KERNEL_CLASSES = ["irregular_voxels", "regular_voxels", "enriched_gather", "fft_x_forward", "fft_y_forward",
+                  "fft_z_green", "fft_y_inverse", "fft_x_inverse", "enriched_residual", "enriched_update",
+                  "scalars"]
 
 _LIB = None
 
@@ -93,6 +98,12 @@ def _lib():
     lib.xfft_apply_precond.restype = ctypes.c_int
     lib.xfft_get_layout.argtypes = [P, I64, I64, D]
     lib.xfft_get_layout.restype = ctypes.c_int
+    lib.xfft_profile.argtypes = [P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, D, I32]
+    lib.xfft_profile.restype = ctypes.c_int
+    lib.xfft_profile_begin.argtypes = [P]
+    lib.xfft_profile_begin.restype = ctypes.c_int
+    lib.xfft_profile_end.argtypes = [P, D, I32]
+    lib.xfft_profile_end.restype = ctypes.c_int
     lib.xfft_destroy.argtypes = [P]
     lib.xfft_destroy.restype = None
     lib.xfft_strerror.argtypes = [ctypes.c_int]
@@ -244,6 +255,29 @@ class Problem:
         r2 = np.zeros(1)
         _check(_lib().xfft_apply_precond(self._h, _PREC[precision], _dp(f), _dp(y), _dp(r2)), "xfft_apply_precond")
         return y, float(r2[0])
+
+    def profile(self, precision="fp32", nrhs=6, nrep=10):
+        """Average per-launch kernel times (ms) of one CG iteration, by kernel class."""
+        ms = np.zeros(len(KERNEL_CLASSES))
+        cnt = np.zeros(len(KERNEL_CLASSES), dtype=np.int32)
+        _check(_lib().xfft_profile(self._h, _PREC[precision], nrhs, nrep, _dp(ms), _ip(cnt)), "xfft_profile")
+        return {k: (float(m), int(c)) for k, m, c in zip(KERNEL_CLASSES, ms, cnt)}
+
+    def profile_begin(self):
+        """Start timing every kernel launch (see profile_end)."""
+        _check(_lib().xfft_profile_begin(self._h), "xfft_profile_begin")
+
+    def profile_end(self):
+        """Per kernel class and precision: (average ms per launch, launches) since profile_begin."""
+        n = 2 * len(KERNEL_CLASSES)
+        ms = np.zeros(n)
+        cnt = np.zeros(n, dtype=np.int32)
+        _check(_lib().xfft_profile_end(self._h, _dp(ms), _ip(cnt)), "xfft_profile_end")
+        out = {}
+        for i, (m, c) in enumerate(zip(ms, cnt)):
+            prec = "fp32" if i < len(KERNEL_CLASSES) else "fp64"
+            out[(KERNEL_CLASSES[i % len(KERNEL_CLASSES)], prec)] = (float(m), int(c))
+        return out
 
     def layout(self, with_arrays=True):
         info = np.zeros(6, dtype=np.int64)
