@@ -97,6 +97,7 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--rtol", type=float, default=1e-10)
+    ap.add_argument("--inner-rtol", type=float, default=1e-4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     args = ap.parse_args()
@@ -115,7 +116,7 @@ def main():
 
     def make(precision, batch):
         return Problem(cfg["n"], cfg["length"], cfg["L"], cfg["phase"], cfg["lame"], rtol=args.rtol,
-                       precision=precision, batch=batch)
+                       precision=precision, batch=batch, inner_rtol=args.inner_rtol)
 
     t0 = time.perf_counter()
     pm = make("mixed", True)
@@ -214,7 +215,7 @@ def main():
         "dtype": "f32 (FP64 refinement)",
         "data": "synthetic",
         "config": {"workload": "spheres128: 128^3, 40 RSA spheres r~U[0.06,0.1]L, contrast 10, 6 unit loads",
-                   "rtol": args.rtol, "precision": "mixed", "batched_loads": 6,
+                   "rtol": args.rtol, "inner_rtol": args.inner_rtol, "precision": "mixed", "batched_loads": 6,
                    "n_enriched": lay["nX"], "n_irregular_voxels": lay["n_irregular_voxels"],
                    "vf": cfg["info"]["vf"]},
         "roofline": roofline,

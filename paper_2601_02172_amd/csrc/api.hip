@@ -112,11 +112,12 @@ int read_flags(xfft_problem *p, int nrhs, std::vector<Flags> &out) {
 template <typename T>
 void cg_iteration(xfft_problem *p, Work<T> &w, const Tables<T> &tb, int nrhs, int parity, int crit) {
     hipStream_t s = p->stream;
-    launch_operator<T>(p, w, tb, w.d, w.de, w.z, w.ze, false, (T)1, nrhs, p->flags, parity, nullptr, s);
-    launch_scalars(p, SC_ALPHA, crit, nrhs, parity, nullptr, s);
+    // the stress integral is only needed when the criterion tracks <sigma> (criterion 0)
+    launch_operator<T>(p, w, tb, w.d, w.de, w.z, w.ze, false, (T)1, nrhs, p->flags, parity, nullptr, s, crit == 0);
+    launch_scalars(p, SC_ALPHA, crit, nrhs, parity, nullptr, s, sizeof(T) == 8);
     launch_green_forward<T>(p, w, tb, w.f, w.z, nrhs, p->flags, parity, s);
     launch_enr_update<T>(p, w, 1, nullptr, nrhs, p->flags, parity, s);
-    launch_scalars(p, SC_BETA, crit, nrhs, parity, nullptr, s);
+    launch_scalars(p, SC_BETA, crit, nrhs, parity, nullptr, s, sizeof(T) == 8);
     launch_green_inverse<T>(p, w, tb, 1, nullptr, nrhs, p->flags, parity, s);
     launch_enr_final<T>(p, w, 1, nrhs, p->flags, parity, s);
 }
@@ -129,7 +130,7 @@ void cg_start(xfft_problem *p, Work<T> &w, const Tables<T> &tb, int nrhs, int cr
     launch_enr_update<T>(p, w, 0, nullptr, nrhs, nullptr, 0, s);
     launch_green_inverse<T>(p, w, tb, 2, nullptr, nrhs, nullptr, 0, s);
     launch_enr_final<T>(p, w, 2, nrhs, nullptr, 0, s);
-    launch_scalars(p, SC_INIT_RES, crit, nrhs, 0, nullptr, s);
+    launch_scalars(p, SC_INIT_RES, crit, nrhs, 0, nullptr, s, sizeof(T) == 8);
 }
 
 // Iterate until no right-hand side is active; returns iterations run.
@@ -162,7 +163,7 @@ int final_outputs(xfft_problem *p, int nrhs, double *avg_host, double *vstress_d
     launch_operator<double>(p, w, p->t64, w.u, w.ue, w.z, w.ze, true, 1.0, nrhs, nullptr, 0, vstress_dev, s);
     double *sum_dev = nullptr;
     HIP_OK(hipMalloc(&sum_dev, sizeof(double) * 7 * nrhs));
-    launch_scalars(p, SC_SUM_ONLY, 0, nrhs, 0, sum_dev, s);
+    launch_scalars(p, SC_SUM_ONLY, 0, nrhs, 0, sum_dev, s, true);
     std::vector<double> sum(7 * nrhs);
     hipError_t e1 = hipMemcpyAsync(sum.data(), sum_dev, sizeof(double) * 7 * nrhs, hipMemcpyDeviceToHost, s);
     hipError_t e2 = hipStreamSynchronize(s);
@@ -204,7 +205,7 @@ int solve_block(xfft_problem *p, int nrhs, const double *ebar_host, std::vector<
     if (p->precision != XFFT_MIXED) {
         // f = b = -r(0)
         launch_operator<double>(p, w, p->t64, nullptr, nullptr, w.f, w.fe, true, -1.0, nrhs, nullptr, 0, nullptr, s);
-        launch_scalars(p, SC_INIT_SIGMA, 0, nrhs, 0, nullptr, s);
+        launch_scalars(p, SC_INIT_SIGMA, 0, nrhs, 0, nullptr, s, true);
         cg_start<double>(p, w, p->t64, nrhs, 0);
         cg_loop<double>(p, w, p->t64, nrhs, 0, &rc);
         if (rc) return rc;
@@ -223,7 +224,7 @@ int solve_block(xfft_problem *p, int nrhs, const double *ebar_host, std::vector<
             // r = b - A u in FP64 (also gives the exact <sigma(u)>)
             launch_operator<double>(p, w, p->t64, o == 0 ? nullptr : w.u, w.ue, w.f, w.fe, true, -1.0, nrhs, nullptr,
                                     0, nullptr, s);
-            launch_scalars(p, SC_INIT_SIGMA, 0, nrhs, 0, nullptr, s);
+            launch_scalars(p, SC_INIT_SIGMA, 0, nrhs, 0, nullptr, s, true);
             launch_round_to_float(p, nrhs, s);
             cg_start<float>(p, w32, p->t32, nrhs, 0);     // outer criterion on the FP64 residual
             rc = read_flags(p, nrhs, fl);
@@ -403,7 +404,7 @@ int profile_impl(xfft_problem *p, Work<T> &w, const Tables<T> &tb, int nrhs, int
     HIP_OK(hipMemsetAsync(w.u, 0, sizeof(T) * 3 * p->g.N * nrhs, s));
     if (p->g.nX) HIP_OK(hipMemsetAsync(w.ue, 0, sizeof(T) * 3 * p->g.nX * nrhs, s));
     launch_operator<T>(p, w, tb, nullptr, nullptr, w.f, w.fe, true, (T)-1, nrhs, nullptr, 0, nullptr, s);
-    launch_scalars(p, SC_INIT_SIGMA, 0, nrhs, 0, nullptr, s);
+    launch_scalars(p, SC_INIT_SIGMA, 0, nrhs, 0, nullptr, s, true);
     cg_start<T>(p, w, tb, nrhs, 0);
     std::vector<Flags> fl;
     rc = read_flags(p, nrhs, fl);
@@ -511,7 +512,7 @@ void xfft_destroy(xfft_problem *p) {
     if (!p) return;
     (void)hipSetDevice(p->device);
     if (p->stream) (void)hipStreamSynchronize(p->stream);
-    void *ptrs[] = {p->Ls, p->phase, p->vmat, p->irr, p->irr_j, p->irr_lab, p->jlist, p->d0, p->partial,
+    void *ptrs[] = {p->Ls, p->phase, p->vmat, p->irr, p->irr_j, p->irr_lab, p->jlist, p->enr_src, p->d0, p->partial,
                     p->scal, p->flags, p->ebar, p->sol_u, p->sol_ue, p->t64.lame, p->t64.d0is, p->t64.irr_L,
                     p->t32.lame, p->t32.d0is, p->t32.irr_L};
     for (void *q : ptrs)
@@ -678,7 +679,7 @@ int xfft_apply_operator(xfft_problem *p, int32_t precision, const double *x, con
         if (nX) HIP_OK(hipMemcpyAsync(w.de, x + 3 * N, sizeof(double) * 3 * nX, hipMemcpyHostToDevice, s));
         launch_operator<double>(p, w, p->t64, w.d, w.de, w.z, w.ze, macro_strain != nullptr, 1.0, 1, nullptr, 0,
                                 nullptr, s);
-        launch_scalars(p, SC_SUM_ONLY, 0, 1, 0, sum_dev, s);
+        launch_scalars(p, SC_SUM_ONLY, 0, 1, 0, sum_dev, s, true);
         HIP_OK(hipMemcpyAsync(y, w.z, sizeof(double) * 3 * N, hipMemcpyDeviceToHost, s));
         if (nX) HIP_OK(hipMemcpyAsync(y + 3 * N, w.ze, sizeof(double) * 3 * nX, hipMemcpyDeviceToHost, s));
     } else {
@@ -689,7 +690,7 @@ int xfft_apply_operator(xfft_problem *p, int32_t precision, const double *x, con
         if (nX) HIP_OK(hipMemcpyAsync(w.de, xf.data() + 3 * N, sizeof(float) * 3 * nX, hipMemcpyHostToDevice, s));
         launch_operator<float>(p, w, p->t32, w.d, w.de, w.z, w.ze, macro_strain != nullptr, 1.0f, 1, nullptr, 0,
                                nullptr, s);
-        launch_scalars(p, SC_SUM_ONLY, 0, 1, 0, sum_dev, s);
+        launch_scalars(p, SC_SUM_ONLY, 0, 1, 0, sum_dev, s, true);
         HIP_OK(hipMemcpyAsync(yf.data(), w.z, sizeof(float) * 3 * N, hipMemcpyDeviceToHost, s));
         if (nX) HIP_OK(hipMemcpyAsync(yf.data() + 3 * N, w.ze, sizeof(float) * 3 * nX, hipMemcpyDeviceToHost, s));
         HIP_OK(hipStreamSynchronize(s));
@@ -727,7 +728,7 @@ int xfft_apply_precond(xfft_problem *p, int32_t precision, const double *f, doub
         launch_green_forward<double>(p, w, p->t64, w.f, nullptr, 1, nullptr, 0, s);
         launch_enr_update<double>(p, w, 0, w.ze, 1, nullptr, 0, s);
         launch_green_inverse<double>(p, w, p->t64, 0, w.z, 1, nullptr, 0, s);
-        launch_scalars(p, SC_SUM_GREEN, 0, 1, 0, sum_dev, s);
+        launch_scalars(p, SC_SUM_GREEN, 0, 1, 0, sum_dev, s, true);
         HIP_OK(hipMemcpyAsync(y, w.z, sizeof(double) * 3 * N, hipMemcpyDeviceToHost, s));
         if (nX) HIP_OK(hipMemcpyAsync(y + 3 * N, w.ze, sizeof(double) * 3 * nX, hipMemcpyDeviceToHost, s));
     } else {
@@ -739,7 +740,7 @@ int xfft_apply_precond(xfft_problem *p, int32_t precision, const double *f, doub
         launch_green_forward<float>(p, w, p->t32, w.f, nullptr, 1, nullptr, 0, s);
         launch_enr_update<float>(p, w, 0, w.ze, 1, nullptr, 0, s);
         launch_green_inverse<float>(p, w, p->t32, 0, w.z, 1, nullptr, 0, s);
-        launch_scalars(p, SC_SUM_GREEN, 0, 1, 0, sum_dev, s);
+        launch_scalars(p, SC_SUM_GREEN, 0, 1, 0, sum_dev, s, false);
         HIP_OK(hipMemcpyAsync(yf.data(), w.z, sizeof(float) * 3 * N, hipMemcpyDeviceToHost, s));
         if (nX) HIP_OK(hipMemcpyAsync(yf.data() + 3 * N, w.ze, sizeof(float) * 3 * nX, hipMemcpyDeviceToHost, s));
         HIP_OK(hipStreamSynchronize(s));
@@ -772,8 +773,25 @@ int xfft_get_layout(xfft_problem *p, int64_t *info, int64_t *jlist, double *d0) 
 }
 
 int xfft_grad_lame(xfft_problem *p, const double *dL_dC, double *grad, double *dC_out) {
-    (void)p; (void)dL_dC; (void)grad; (void)dC_out;
-    return XFFT_EINVAL;
+    if (!p || (!grad && !dC_out) || (grad && !dL_dC)) return XFFT_EINVAL;
+    if (!p->sol_unit_basis || !p->sol_u) return XFFT_EINVAL;
+    HIP_OK(hipSetDevice(p->device));
+    const int np = p->g.nphase;
+    std::vector<double> dC((size_t)np * 72);
+    const int rc = grad_tables(p, dC.data());
+    if (rc == -1) return XFFT_EINVAL;
+    if (rc == -2) return XFFT_ENOMEM;
+    if (rc) return XFFT_EDEVICE;
+    if (dC_out) std::memcpy(dC_out, dC.data(), sizeof(double) * dC.size());
+    if (grad) {
+        for (int ph = 0; ph < np; ++ph)
+            for (int j = 0; j < 2; ++j) {
+                double acc = 0.0;
+                for (int q = 0; q < 36; ++q) acc += dL_dC[q] * dC[(ph * 2 + j) * 36 + q];
+                grad[2 * ph + j] = acc;
+            }
+    }
+    return XFFT_OK;
 }
 
 int xfft_batch_solve(xfft_problem *const *ps, int32_t nprob, double *c_eff, xfft_stats *stats) {

@@ -16,6 +16,7 @@ struct ScArgs {
     const double *partial;
     int nslots;
     int s0, n;            // slot range to sum
+    int s1, n1;           // second slot range (0 length when unused)
     Scalars *scal;
     Flags *flags;
     double volume;
@@ -38,6 +39,11 @@ __global__ __launch_bounds__(256) void k_scalars(ScArgs A) {
     for (int i = threadIdx.x; i < A.n; i += blockDim.x) {
 #pragma unroll
         for (int q = 0; q < 7; ++q) v[q] += P[(int64_t)i * NPART + q];
+    }
+    const double *P1 = A.partial + ((int64_t)r * A.nslots + A.s1) * NPART;
+    for (int i = threadIdx.x; i < A.n1; i += blockDim.x) {
+#pragma unroll
+        for (int q = 0; q < 7; ++q) v[q] += P1[(int64_t)i * NPART + q];
     }
     block_sum<7>(v, red);
     if (threadIdx.x != 0) return;
@@ -165,7 +171,8 @@ __global__ void k_accumulate(int64_t n, const Flags *flags, double *dst, const f
 
 }  // namespace
 
-void launch_scalars(xfft_problem *p, int op, int crit, int nrhs, int parity, double *sum_out, hipStream_t s) {
+void launch_scalars(xfft_problem *p, int op, int crit, int nrhs, int parity, double *sum_out, hipStream_t s,
+                    bool fp64) {
     ScArgs A;
     A.partial = p->partial;
     A.nslots = p->nslots;
@@ -173,9 +180,13 @@ void launch_scalars(xfft_problem *p, int op, int crit, int nrhs, int parity, dou
     if (op == SC_INIT_SIGMA || op == SC_ALPHA || op == SC_SUM_ONLY) {
         A.s0 = L.fe0;
         A.n = L.fe_n + L.cut_n + L.enr_n;
+        A.s1 = 0;
+        A.n1 = 0;
     } else {
         A.s0 = L.grn0;
-        A.n = L.grn_n + L.eu_n;
+        A.n = fp64 ? green_blocks<double>(p->g) : green_blocks<float>(p->g);
+        A.s1 = L.eu0;
+        A.n1 = L.eu_n;
     }
     A.scal = p->scal;
     A.flags = p->flags;

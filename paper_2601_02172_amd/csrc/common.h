@@ -170,6 +170,7 @@ struct xfft_problem {
     int32_t *irr_j = nullptr;      // [nirr][8] enriched index per corner or -1
     int32_t *irr_lab = nullptr;    // [nirr][6][2] element labels: uncut (both) or (+ side, - side)
     int32_t *jlist = nullptr;      // [nX]
+    int32_t *enr_src = nullptr;    // [nX][8] 8 * irregular voxel + corner feeding enriched node j, or -1
     double *d0 = nullptr;          // [nX]
     int64_t n_cut_elements = 0, n_multilabel = 0;
     std::vector<double> lame_host;

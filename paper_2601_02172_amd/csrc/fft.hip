@@ -17,6 +17,7 @@
 //   phi_ab = (theta_a + theta_b) / 2, {a, b, c} = {0, 1, 2};
 // S(0) = 0 maps the zero frequency to zero (mean-free FE field).
 #include "kernels.h"
+#include "fft_lines.h"
 
 namespace xfft {
 
@@ -240,7 +241,8 @@ __device__ __forceinline__ void green_apply(T s0, T c0, T s1, T c1, T s2, T c2, 
 
 template <typename T>
 __global__ __launch_bounds__(512) void k_fft_z_green(FftArgs A, FftPlan pl, const cpx<T> *tw, const T *h0,
-                                                      const T *h1, const T *h2, cpx<T> *spec, int tk) {
+                                                      const T *h1, const T *h2, cpx<T> *spec, int tk, int64_t sz,
+                                                      int64_t sy) {
     extern __shared__ unsigned char smem_raw[];
     cpx<T> *sh = reinterpret_cast<cpx<T> *>(smem_raw);
     __shared__ double red[8];
@@ -253,13 +255,12 @@ __global__ __launch_bounds__(512) void k_fft_z_green(FftArgs A, FftPlan pl, cons
     const int ky = blockIdx.x / ntiles;
     const int kx0 = tile * tk;
     cpx<T> *base = spec + (int64_t)r * 3 * A.specN;
-    const int64_t zstride = (int64_t)n1 * nh;
     for (int idx = threadIdx.x; idx < 3 * tk * n2; idx += blockDim.x) {
         const int kl = idx % tk, rest = idx / tk;
         const int zz = rest % n2, c = rest / n2;
         const int kx = kx0 + kl;
         sh[(c * tk + kl) * lstride + zz] =
-            (kx < nh) ? base[(int64_t)c * A.specN + zz * zstride + (int64_t)ky * nh + kx] : cpx<T>{0, 0};
+            (kx < nh) ? base[(int64_t)c * A.specN + zz * sz + (int64_t)ky * sy + kx] : cpx<T>{0, 0};
     }
     __syncthreads();
     lds_fft<T, false>(sh, 3 * tk, lstride, pl, tw);
@@ -293,7 +294,7 @@ __global__ __launch_bounds__(512) void k_fft_z_green(FftArgs A, FftPlan pl, cons
         const int kl = idx % tk, rest = idx / tk;
         const int zz = rest % n2, c = rest / n2;
         const int kx = kx0 + kl;
-        if (kx < nh) base[(int64_t)c * A.specN + zz * zstride + (int64_t)ky * nh + kx] = sh[(c * tk + kl) * lstride + zz];
+        if (kx < nh) base[(int64_t)c * A.specN + zz * sz + (int64_t)ky * sy + kx] = sh[(c * tk + kl) * lstride + zz];
     }
     double v[1] = {part};
     block_sum<1>(v, red);
@@ -359,6 +360,216 @@ __global__ __launch_bounds__(256) void k_fft_x_inv(FftArgs A, FftPlan pl, const 
     }
 }
 
+// ---------------------------------------------------------------- xy plane kernels (n0 == n1 == N)
+// One workgroup per (component, z plane, load).  LDS holds the whole plane; the
+// x transform runs on row pairs packed as complex lines, the y transform on the
+// kx columns.  Spectrum layout [c][ky][kz][kx] (kx fastest).
+template <int N> struct PlaneCfg {
+    static constexpr int NH = N / 2 + 1;
+    static constexpr int NP = N / 2;
+    static constexpr int LS = N + 1;
+    static constexpr int NT = 1024;
+    static constexpr int ELEMS = NH * LS;      // >= NP * LS
+};
+
+template <typename T> __device__ __forceinline__ bool active_of(const Flags *flags, int parity, int r) {
+    return flags == nullptr || flags[r].active[parity] != 0;
+}
+
+template <typename T, int N>
+__global__ __launch_bounds__(1024) void k_fft_plane_fwd(FftArgs A, const cpx<T> *tw, T *f, const T *z,
+                                                         cpx<T> *spec) {
+    using C = PlaneCfg<N>;
+    extern __shared__ unsigned char smem_raw[];
+    cpx<T> *sh = reinterpret_cast<cpx<T> *>(smem_raw);
+    const int r = blockIdx.y;
+    if (!active_rhs(A, r)) return;
+    const int plane = blockIdx.x;                 // c * n2 + kz
+    const int c = plane / A.n2, kz = plane - c * A.n2;
+    const T alpha = z ? (T)A.scal[r].alpha : (T)0;
+    T *fr = f + (int64_t)r * 3 * A.N + (int64_t)plane * N * N;
+    const T *zr = z ? z + (int64_t)r * 3 * A.N + (int64_t)plane * N * N : nullptr;
+    // load rows (fused residual update), pack row pairs
+    for (int idx = threadIdx.x; idx < C::NP * N; idx += C::NT) {
+        const int pp = idx / N, x = idx - pp * N;
+        const int o0 = (2 * pp) * N + x, o1 = o0 + N;
+        T a = fr[o0], b = fr[o1];
+        if (zr) {
+            a -= alpha * zr[o0];
+            b -= alpha * zr[o1];
+            fr[o0] = a;
+            fr[o1] = b;
+        }
+        sh[pp * C::LS + x] = {a, b};
+    }
+    __syncthreads();
+    fft_lines<T, N, C::NP, C::NT, false>(sh, tw);
+    // split the packed spectra into the two rows; transpose to kx-major columns
+    constexpr int NOUT = C::NP * C::NH;
+    constexpr int MO = (NOUT + C::NT - 1) / C::NT;
+    cpx<T> ra[MO], rb[MO];
+#pragma unroll
+    for (int i = 0; i < MO; ++i) {
+        const int idx = threadIdx.x + i * C::NT;
+        if (idx < NOUT) {
+            const int pp = idx / C::NH, kx = idx - pp * C::NH;
+            const cpx<T> Zk = sh[pp * C::LS + kx];
+            const cpx<T> Zm = sh[pp * C::LS + (kx == 0 ? 0 : N - kx)];
+            ra[i] = {(T)0.5 * (Zk.x + Zm.x), (T)0.5 * (Zk.y - Zm.y)};
+            rb[i] = {(T)0.5 * (Zk.y + Zm.y), (T)-0.5 * (Zk.x - Zm.x)};
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < MO; ++i) {
+        const int idx = threadIdx.x + i * C::NT;
+        if (idx < NOUT) {
+            const int pp = idx / C::NH, kx = idx - pp * C::NH;
+            sh[kx * C::LS + 2 * pp] = ra[i];
+            sh[kx * C::LS + 2 * pp + 1] = rb[i];
+        }
+    }
+    __syncthreads();
+    fft_lines<T, N, C::NH, C::NT, false>(sh, tw);
+    cpx<T> *sr = spec + (int64_t)r * 3 * A.specN + (int64_t)c * A.specN;
+    for (int idx = threadIdx.x; idx < N * C::NH; idx += C::NT) {
+        const int ky = idx / C::NH, kx = idx - ky * C::NH;
+        sr[((int64_t)ky * A.n2 + kz) * C::NH + kx] = sh[kx * C::LS + ky];
+    }
+}
+
+template <typename T, int N>
+__global__ __launch_bounds__(1024) void k_fft_plane_inv(FftArgs A, const cpx<T> *tw, const cpx<T> *spec, int mode,
+                                                         T *out, T *u, T *d) {
+    using C = PlaneCfg<N>;
+    extern __shared__ unsigned char smem_raw[];
+    cpx<T> *sh = reinterpret_cast<cpx<T> *>(smem_raw);
+    const int r = blockIdx.y;
+    if (!active_rhs(A, r)) return;
+    const int plane = blockIdx.x;
+    const int c = plane / A.n2, kz = plane - c * A.n2;
+    const cpx<T> *sr = spec + (int64_t)r * 3 * A.specN + (int64_t)c * A.specN;
+    for (int idx = threadIdx.x; idx < N * C::NH; idx += C::NT) {
+        const int ky = idx / C::NH, kx = idx - ky * C::NH;
+        sh[kx * C::LS + ky] = sr[((int64_t)ky * A.n2 + kz) * C::NH + kx];
+    }
+    __syncthreads();
+    fft_lines<T, N, C::NH, C::NT, true>(sh, tw);
+    // rebuild packed row pairs Z_k = A_k + i B_k over the full x spectrum
+    constexpr int NOUT = C::NP * N;
+    constexpr int MO = (NOUT + C::NT - 1) / C::NT;
+    cpx<T> rz[MO];
+#pragma unroll
+    for (int i = 0; i < MO; ++i) {
+        const int idx = threadIdx.x + i * C::NT;
+        if (idx < NOUT) {
+            const int pp = idx / N, k = idx - pp * N;
+            const bool lo = k < C::NH;
+            const int kk = lo ? k : N - k;
+            cpx<T> Av = sh[kk * C::LS + 2 * pp], Bv = sh[kk * C::LS + 2 * pp + 1];
+            if (!lo) { Av.y = -Av.y; Bv.y = -Bv.y; }
+            rz[i] = {Av.x - Bv.y, Av.y + Bv.x};
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < MO; ++i) {
+        const int idx = threadIdx.x + i * C::NT;
+        if (idx < NOUT) {
+            const int pp = idx / N, k = idx - pp * N;
+            sh[pp * C::LS + k] = rz[i];
+        }
+    }
+    __syncthreads();
+    fft_lines<T, N, C::NP, C::NT, true>(sh, tw);
+    const int64_t base = (int64_t)r * 3 * A.N + (int64_t)plane * N * N;
+    T alpha = 0, beta = 0;
+    if (mode == 1) { alpha = (T)A.scal[r].alpha; beta = (T)A.scal[r].beta; }
+    for (int idx = threadIdx.x; idx < C::NP * N; idx += C::NT) {
+        const int pp = idx / N, x = idx - pp * N;
+        const cpx<T> yv = sh[pp * C::LS + x];
+        const int64_t o0 = base + (2 * pp) * N + x, o1 = o0 + N;
+        if (mode == 0) {
+            out[o0] = yv.x;
+            out[o1] = yv.y;
+        } else if (mode == 1) {
+            const T d0 = d[o0], d1 = d[o1];
+            u[o0] += alpha * d0;
+            u[o1] += alpha * d1;
+            d[o0] = yv.x + beta * d0;
+            d[o1] = yv.y + beta * d1;
+        } else {
+            d[o0] = yv.x;
+            d[o1] = yv.y;
+        }
+    }
+}
+
+// ---------------------------------------------------------------- z pass, compile-time length
+// Element (c, kz, ky, kx) of the spectrum at c * specN + kz * sz + ky * sy + kx.
+template <typename T, int N2, int TK>
+__global__ __launch_bounds__(512) void k_fft_z_t(FftArgs A, const cpx<T> *tw, const T *h0, const T *h1,
+                                                  const T *h2, cpx<T> *spec, int64_t sz, int64_t sy) {
+    constexpr int LS = N2 + 1;
+    constexpr int NL = 3 * TK;
+    extern __shared__ unsigned char smem_raw[];
+    cpx<T> *sh = reinterpret_cast<cpx<T> *>(smem_raw);
+    __shared__ double red[8];
+    const int r = blockIdx.y;
+    if (!active_rhs(A, r)) return;
+    const int nh = A.nh;
+    const int ntiles = (nh + TK - 1) / TK;
+    const int tile = blockIdx.x % ntiles;
+    const int ky = blockIdx.x / ntiles;
+    const int kx0 = tile * TK;
+    cpx<T> *base = spec + (int64_t)r * 3 * A.specN + (int64_t)ky * sy + kx0;
+    for (int idx = threadIdx.x; idx < NL * N2; idx += 512) {
+        const int kl = idx % TK, rest = idx / TK;
+        const int zz = rest % N2, c = rest / N2;
+        sh[(c * TK + kl) * LS + zz] = (kx0 + kl < nh) ? base[(int64_t)c * A.specN + zz * sz + kl] : cpx<T>{0, 0};
+    }
+    __syncthreads();
+    fft_lines<T, N2, NL, 512, false>(sh, tw);
+    double part = 0.0;
+    const T scale = (T)(1.0 / ((double)A.n0 * (double)A.n1 * (double)N2));
+    for (int idx = threadIdx.x; idx < TK * N2; idx += 512) {
+        const int kl = idx % TK, zz = idx / TK;
+        const int kx = kx0 + kl;
+        if (kx < nh) {
+            cpx<T> fv[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) fv[c] = sh[(c * TK + kl) * LS + zz];
+            const cpx<T> f0[3] = {fv[0], fv[1], fv[2]};
+            green_apply<T>(h0[2 * kx], h0[2 * kx + 1], h1[2 * ky], h1[2 * ky + 1], h2[2 * zz], h2[2 * zz + 1], fv,
+                           kx == 0 && ky == 0 && zz == 0);
+            double q = 0.0;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                fv[c].x *= scale;
+                fv[c].y *= scale;
+                q += (double)f0[c].x * (double)fv[c].x + (double)f0[c].y * (double)fv[c].y;
+                sh[(c * TK + kl) * LS + zz] = fv[c];
+            }
+            part += ((kx == 0 || 2 * kx == A.n0) ? 1.0 : 2.0) * q;
+        }
+    }
+    __syncthreads();
+    fft_lines<T, N2, NL, 512, true>(sh, tw);
+    for (int idx = threadIdx.x; idx < NL * N2; idx += 512) {
+        const int kl = idx % TK, rest = idx / TK;
+        const int zz = rest % N2, c = rest / N2;
+        if (kx0 + kl < nh) base[(int64_t)c * A.specN + zz * sz + kl] = sh[(c * TK + kl) * LS + zz];
+    }
+    double v[1] = {part};
+    block_sum<1>(v, red);
+    if (threadIdx.x == 0) {
+        double *P = A.partial + ((int64_t)r * A.nslots + A.slot0 + blockIdx.x) * NPART;
+        P[0] = v[0];
+#pragma unroll
+        for (int q = 1; q < 7; ++q) P[q] = 0.0;
+    }
+}
+
 template <typename T> int pairs_for(int n0) {
     // limit: butterflies per stage <= MAXB * 256 (radix 2 worst case) and LDS <= 64 KiB
     int p = (MAXB * 256 * 2) / n0;
@@ -389,45 +600,123 @@ FftArgs fft_args(xfft_problem *p, const Flags *flags, int parity) {
 
 }  // namespace
 
-// The z pass uses the FP64 tile width in both precisions so that its number of
-// blocks (= partial-sum slots) does not depend on the precision.
+// The generic z pass (runtime line length) uses the FP64 tile width in both precisions.
 static int tk_z(const Geometry &g) { return tk_for<double>(g.n2, 3, 512); }
 
-int green_slots(const Geometry &g) { return g.n1 * ((g.nh + tk_z(g) - 1) / tk_z(g)); }
+static bool plane_size(int n) { return n == 16 || n == 32 || n == 48 || n == 64 || n == 96 || n == 128; }
+static bool ztmpl_size(int n) { return plane_size(n) || n == 256; }
+
+template <typename T> static bool plane_path(const Geometry &g) {
+    return g.n0 == g.n1 && plane_size(g.n0) &&
+           (size_t)(g.n0 / 2 + 1) * (g.n0 + 1) * sizeof(cpx<T>) <= (size_t)160 * 1024;
+}
+template <typename T> static constexpr int tkz_t() { return sizeof(T) == 8 ? 8 : 16; }
+
+template <typename T> int green_blocks(const Geometry &g) {
+    const int tk = ztmpl_size(g.n2) ? tkz_t<T>() : tk_z(g);
+    return g.n1 * ((g.nh + tk - 1) / tk);
+}
+template int green_blocks<double>(const Geometry &);
+template int green_blocks<float>(const Geometry &);
+
+int green_slots(const Geometry &g) {
+    const int a = green_blocks<double>(g), b = green_blocks<float>(g);
+    return a > b ? a : b;
+}
+
+template <typename K> static void allow_lds(K kernel, size_t bytes) {
+    if (bytes > 65536) (void)hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+template <typename T, int N>
+static void plane_fwd(FftArgs A, dim3 grid, hipStream_t s, const cpx<T> *tw, T *f, const T *z, cpx<T> *spec) {
+    const size_t lds = (size_t)PlaneCfg<N>::ELEMS * sizeof(cpx<T>);
+    static bool init = false;
+    if (!init) { allow_lds(k_fft_plane_fwd<T, N>, lds); init = true; }
+    k_fft_plane_fwd<T, N><<<grid, PlaneCfg<N>::NT, lds, s>>>(A, tw, f, z, spec);
+}
+template <typename T, int N>
+static void plane_inv(FftArgs A, dim3 grid, hipStream_t s, const cpx<T> *tw, const cpx<T> *spec, int mode, T *out,
+                      T *u, T *d) {
+    const size_t lds = (size_t)PlaneCfg<N>::ELEMS * sizeof(cpx<T>);
+    static bool init = false;
+    if (!init) { allow_lds(k_fft_plane_inv<T, N>, lds); init = true; }
+    k_fft_plane_inv<T, N><<<grid, PlaneCfg<N>::NT, lds, s>>>(A, tw, spec, mode, out, u, d);
+}
+template <typename T, int N2>
+static void zpass(FftArgs A, dim3 grid, hipStream_t s, const Tables<T> &tb, cpx<T> *spec, int64_t sz, int64_t sy) {
+    constexpr int TK = tkz_t<T>();
+    const size_t lds = (size_t)3 * TK * (N2 + 1) * sizeof(cpx<T>);
+    static bool init = false;
+    if (!init) { allow_lds(k_fft_z_t<T, N2, TK>, lds); init = true; }
+    k_fft_z_t<T, N2, TK><<<grid, 512, lds, s>>>(A, tb.tw[2], tb.half[0], tb.half[1], tb.half[2], spec, sz, sy);
+}
 
 template <typename T>
 void launch_green_forward(xfft_problem *p, Work<T> &w, const Tables<T> &tb, T *f, const T *z, int nrhs,
                           const Flags *flags, int parity, hipStream_t s) {
     const Geometry &g = p->g;
     FftArgs A = fft_args<T>(p, flags, parity);
-    {
-        const int pp = pairs_for<T>(g.n0);
-        const int64_t npairs = (int64_t)3 * g.n2 * g.n1 / 2;
-        dim3 grid((unsigned)((npairs + pp - 1) / pp), nrhs);
-        const size_t lds = (size_t)pp * (g.n0 + 1) * sizeof(cpx<T>);
+    const bool plane = plane_path<T>(g);
+    int64_t sz, sy;
+    if (plane) {
+        sz = g.nh;
+        sy = (int64_t)g.n2 * g.nh;
+        dim3 grid(3 * g.n2, nrhs);
         xfft_prof_mark(p, -1, s);
-        k_fft_x_fwd<T><<<grid, 256, lds, s>>>(A, p->plan[0], tb.tw[0], f, z, w.spec, pp);
+        switch (g.n0) {
+            case 16: plane_fwd<T, 16>(A, grid, s, tb.tw[0], f, z, w.spec); break;
+            case 32: plane_fwd<T, 32>(A, grid, s, tb.tw[0], f, z, w.spec); break;
+            case 48: plane_fwd<T, 48>(A, grid, s, tb.tw[0], f, z, w.spec); break;
+            case 64: plane_fwd<T, 64>(A, grid, s, tb.tw[0], f, z, w.spec); break;
+            case 96: plane_fwd<T, 96>(A, grid, s, tb.tw[0], f, z, w.spec); break;
+            default: plane_fwd<T, 128>(A, grid, s, tb.tw[0], f, z, w.spec); break;
+        }
         xfft_prof_mark(p, K_FFT_X_FWD + (sizeof(T) == 8 ? K_COUNT : 0), s);
+    } else {
+        sz = (int64_t)g.n1 * g.nh;
+        sy = g.nh;
+        {
+            const int pp = pairs_for<T>(g.n0);
+            const int64_t npairs = (int64_t)3 * g.n2 * g.n1 / 2;
+            dim3 grid((unsigned)((npairs + pp - 1) / pp), nrhs);
+            const size_t lds = (size_t)pp * (g.n0 + 1) * sizeof(cpx<T>);
+            xfft_prof_mark(p, -1, s);
+            k_fft_x_fwd<T><<<grid, 256, lds, s>>>(A, p->plan[0], tb.tw[0], f, z, w.spec, pp);
+            xfft_prof_mark(p, K_FFT_X_FWD + (sizeof(T) == 8 ? K_COUNT : 0), s);
+        }
+        {
+            const int tk = tk_for<T>(g.n1, 1, 256);
+            dim3 grid(3 * g.n2 * ((g.nh + tk - 1) / tk), nrhs);
+            const size_t lds = (size_t)tk * (g.n1 + 1) * sizeof(cpx<T>);
+            xfft_prof_mark(p, -1, s);
+            k_fft_y<T, false><<<grid, 256, lds, s>>>(A, p->plan[1], tb.tw[1], w.spec, tk);
+            xfft_prof_mark(p, K_FFT_Y_FWD + (sizeof(T) == 8 ? K_COUNT : 0), s);
+        }
     }
     {
-        const int tk = tk_for<T>(g.n1, 1, 256);
-        dim3 grid(3 * g.n2 * ((g.nh + tk - 1) / tk), nrhs);
-        const size_t lds = (size_t)tk * (g.n1 + 1) * sizeof(cpx<T>);
-        xfft_prof_mark(p, -1, s);
-        k_fft_y<T, false><<<grid, 256, lds, s>>>(A, p->plan[1], tb.tw[1], w.spec, tk);
-        xfft_prof_mark(p, K_FFT_Y_FWD + (sizeof(T) == 8 ? K_COUNT : 0), s);
-    }
-    {
-        const int tk = tk_z(g);
         A.slot0 = p->slots.grn0;
-        dim3 grid(g.n1 * ((g.nh + tk - 1) / tk), nrhs);
-        const size_t lds = (size_t)3 * tk * (g.n2 + 1) * sizeof(cpx<T>);
+        dim3 grid(green_blocks<T>(g), nrhs);
         xfft_prof_mark(p, -1, s);
-        k_fft_z_green<T><<<grid, 512, lds, s>>>(A, p->plan[2], tb.tw[2], tb.half[0], tb.half[1], tb.half[2], w.spec,
-                                                 tk);
+        if (ztmpl_size(g.n2)) {
+            switch (g.n2) {
+                case 16: zpass<T, 16>(A, grid, s, tb, w.spec, sz, sy); break;
+                case 32: zpass<T, 32>(A, grid, s, tb, w.spec, sz, sy); break;
+                case 48: zpass<T, 48>(A, grid, s, tb, w.spec, sz, sy); break;
+                case 64: zpass<T, 64>(A, grid, s, tb, w.spec, sz, sy); break;
+                case 96: zpass<T, 96>(A, grid, s, tb, w.spec, sz, sy); break;
+                case 128: zpass<T, 128>(A, grid, s, tb, w.spec, sz, sy); break;
+                default: zpass<T, 256>(A, grid, s, tb, w.spec, sz, sy); break;
+            }
+        } else {
+            const int tk = tk_z(g);
+            const size_t lds = (size_t)3 * tk * (g.n2 + 1) * sizeof(cpx<T>);
+            k_fft_z_green<T><<<grid, 512, lds, s>>>(A, p->plan[2], tb.tw[2], tb.half[0], tb.half[1], tb.half[2],
+                                                     w.spec, tk, sz, sy);
+        }
         xfft_prof_mark(p, K_FFT_Z_GREEN + (sizeof(T) == 8 ? K_COUNT : 0), s);
     }
-    {
+    if (!plane) {
         const int tk = tk_for<T>(g.n1, 1, 256);
         dim3 grid(3 * g.n2 * ((g.nh + tk - 1) / tk), nrhs);
         const size_t lds = (size_t)tk * (g.n1 + 1) * sizeof(cpx<T>);
@@ -442,12 +731,24 @@ void launch_green_inverse(xfft_problem *p, Work<T> &w, const Tables<T> &tb, int 
                           const Flags *flags, int parity, hipStream_t s) {
     const Geometry &g = p->g;
     FftArgs A = fft_args<T>(p, flags, parity);
-    const int pp = pairs_for<T>(g.n0);
-    const int64_t npairs = (int64_t)3 * g.n2 * g.n1 / 2;
-    dim3 grid((unsigned)((npairs + pp - 1) / pp), nrhs);
-    const size_t lds = (size_t)pp * (g.n0 + 1) * sizeof(cpx<T>);
     xfft_prof_mark(p, -1, s);
-    k_fft_x_inv<T><<<grid, 256, lds, s>>>(A, p->plan[0], tb.tw[0], w.spec, mode, out, w.u, w.d, pp);
+    if (plane_path<T>(g)) {
+        dim3 grid(3 * g.n2, nrhs);
+        switch (g.n0) {
+            case 16: plane_inv<T, 16>(A, grid, s, tb.tw[0], w.spec, mode, out, w.u, w.d); break;
+            case 32: plane_inv<T, 32>(A, grid, s, tb.tw[0], w.spec, mode, out, w.u, w.d); break;
+            case 48: plane_inv<T, 48>(A, grid, s, tb.tw[0], w.spec, mode, out, w.u, w.d); break;
+            case 64: plane_inv<T, 64>(A, grid, s, tb.tw[0], w.spec, mode, out, w.u, w.d); break;
+            case 96: plane_inv<T, 96>(A, grid, s, tb.tw[0], w.spec, mode, out, w.u, w.d); break;
+            default: plane_inv<T, 128>(A, grid, s, tb.tw[0], w.spec, mode, out, w.u, w.d); break;
+        }
+    } else {
+        const int pp = pairs_for<T>(g.n0);
+        const int64_t npairs = (int64_t)3 * g.n2 * g.n1 / 2;
+        dim3 grid((unsigned)((npairs + pp - 1) / pp), nrhs);
+        const size_t lds = (size_t)pp * (g.n0 + 1) * sizeof(cpx<T>);
+        k_fft_x_inv<T><<<grid, 256, lds, s>>>(A, p->plan[0], tb.tw[0], w.spec, mode, out, w.u, w.d, pp);
+    }
     xfft_prof_mark(p, K_FFT_X_INV + (sizeof(T) == 8 ? K_COUNT : 0), s);
 }
 

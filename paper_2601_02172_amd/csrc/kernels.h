@@ -7,6 +7,7 @@ namespace xfft {
 
 SlotLayout slot_layout(const Geometry &g);
 int green_slots(const Geometry &g);
+template <typename T> int green_blocks(const Geometry &g);
 
 // Operator r(x) = A x + (macro-strain term) on up to nrhs right-hand sides.
 // x/xe may be null (zero input).  sign multiplies the outputs.  When flags is
@@ -15,7 +16,7 @@ int green_slots(const Geometry &g);
 template <typename T>
 void launch_operator(xfft_problem *p, Work<T> &w, const Tables<T> &tb, const T *x, const T *xe, T *y, T *ye,
                      bool use_ebar, T sign, int nrhs, const Flags *flags, int parity, double *vstress,
-                     hipStream_t s);
+                     hipStream_t s, bool stress = true);
 
 // Green operator passes.  mode_x_fwd: the residual update f -= alpha z is fused
 // when z is non-null.  The z pass writes the Parseval partials.
@@ -41,11 +42,17 @@ void launch_enr_final(xfft_problem *p, Work<T> &w, int mode, int nrhs, const Fla
 
 // Scalar recurrences (one block per right-hand side).
 enum ScalarOp { SC_INIT_SIGMA = 0, SC_INIT_RES = 1, SC_ALPHA = 2, SC_BETA = 3, SC_SUM_ONLY = 4, SC_SUM_GREEN = 5 };
-void launch_scalars(xfft_problem *p, int op, int crit, int nrhs, int parity, double *sum_out, hipStream_t s);
+// fp64 selects the Green-pass slot count of the FP64 (true) or FP32 (false) kernels.
+void launch_scalars(xfft_problem *p, int op, int crit, int nrhs, int parity, double *sum_out, hipStream_t s,
+                    bool fp64);
 
 // Vector helpers for iterative refinement.
 void launch_round_to_float(xfft_problem *p, int nrhs, hipStream_t s);       // w32.f/fe <- w64.f/fe, w32.u/ue <- 0
 void launch_accumulate_correction(xfft_problem *p, int nrhs, hipStream_t s); // w64.u/ue += w32.u/ue
+
+// dC[nphase][2][6][6] from the stored unit-load solutions (0 ok, -1 too many
+// phases, -2 allocation, -3 device error).
+int grad_tables(xfft_problem *p, double *dC_host);
 
 // Setup.
 int run_setup(xfft_problem *p, const double *L_dev_raw);

@@ -32,7 +32,7 @@ struct OpArgs {
     T sign;
     const Flags *flags;
     int parity;
-    const int32_t *vmat, *irr, *irr_j, *irr_lab, *jlist;
+    const int32_t *vmat, *irr, *irr_j, *irr_lab, *jlist, *enr_src;
     const T *d0is, *lame;
     const double *irr_L64;    // [nirr][8] corner level set (FP64 for every precision)
     T *cutbuf;
@@ -71,32 +71,89 @@ __device__ __forceinline__ void store_vstress(double *vs, int64_t N, int64_t v, 
 }
 
 // ---------------------------------------------------------------- regular voxel: 6 Kuhn tets
-template <int t, typename T, bool EB>
-__device__ __forceinline__ void regular_tet(const T (&U)[8][3], const Sym<T> &eb, T lamV, T mu2V, T (&F)[8][3],
-                                            Sym<T> &S) {
-    T v[4][3];
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int i = 0; i < 3; ++i) v[a][i] = U[tet_corner(t, a)][i];
-    Sym<T> e = sym_of(kuhn_grad<t>(v));
+// The six elements of a voxel use 12 distinct edges: 3 first edges 0 -> e_a,
+// 6 middle edges e_a -> e_a + e_b and 3 last edges 7 - e_c -> 7.  The element
+// with axis order (a, b, c) has displacement-gradient columns (first a, middle
+// ab, last c); its stress columns are the forces of those edges (force on the
+// end corner, minus on the start corner).  Corner forces are assembled from
+// the 12 edge forces.  lamV, muV are lambda and mu times the element volume.
+template <typename T> struct EdgeSet {
+    T first[3][3], mid[3][3][3], last[3][3];   // [axis...][component]
+};
+
+template <int a, int b, int c, typename T, bool EB, bool ST>
+__device__ __forceinline__ void kuhn_tet_edges(const EdgeSet<T> &E, const T (&eb)[3][3], T lamV, T muV,
+                                               EdgeSet<T> &G, Sym<T> &S) {
+    const T *P = E.first[a], *Q = E.mid[a][b], *R = E.last[c];
+    T ea = P[a], ebb = Q[b], ec = R[c];
+    T gab = Q[a] + P[b], gac = R[a] + P[c], gbc = R[b] + Q[c];
     if constexpr (EB) {
-        e.xx += eb.xx; e.yy += eb.yy; e.zz += eb.zz; e.yz += eb.yz; e.xz += eb.xz; e.xy += eb.xy;
+        ea += eb[a][a]; ebb += eb[b][b]; ec += eb[c][c];
+        gab += (T)2 * eb[a][b]; gac += (T)2 * eb[a][c]; gbc += (T)2 * eb[b][c];
     }
-    const Sym<T> s = hooke(e, lamV, mu2V);
-    kuhn_scatter<t>(s, F);
-    sym_axpy(S, (T)1, s);
+    const T lt = lamV * (ea + ebb + ec);
+    const T mu2 = muV + muV;
+    const T saa = lt + mu2 * ea, sbb = lt + mu2 * ebb, scc = lt + mu2 * ec;
+    const T sab = muV * gab, sac = muV * gac, sbc = muV * gbc;
+    // column a -> first edge a (shared by (a,b,c) and (a,c,b): accumulate)
+    G.first[a][a] += saa; G.first[a][b] += sab; G.first[a][c] += sac;
+    // column b -> middle edge ab (used once)
+    G.mid[a][b][a] = sab; G.mid[a][b][b] = sbb; G.mid[a][b][c] = sbc;
+    // column c -> last edge c (shared by (a,b,c) and (b,a,c))
+    G.last[c][a] += sac; G.last[c][b] += sbc; G.last[c][c] += scc;
+    if constexpr (ST) {
+        // tensor components by global axis
+        T sx[3][3];
+        sx[a][a] = saa; sx[b][b] = sbb; sx[c][c] = scc;
+        sx[a][b] = sx[b][a] = sab; sx[a][c] = sx[c][a] = sac; sx[b][c] = sx[c][b] = sbc;
+        S.xx += sx[0][0]; S.yy += sx[1][1]; S.zz += sx[2][2];
+        S.yz += sx[1][2]; S.xz += sx[0][2]; S.xy += sx[0][1];
+    }
 }
 
-template <typename T, bool EB>
-__device__ __forceinline__ void regular_voxel(const T (&U)[8][3], const Sym<T> &eb, T lamV, T mu2V, T (&F)[8][3],
-                                              Sym<T> &S) {
-    regular_tet<0, T, EB>(U, eb, lamV, mu2V, F, S);
-    regular_tet<1, T, EB>(U, eb, lamV, mu2V, F, S);
-    regular_tet<2, T, EB>(U, eb, lamV, mu2V, F, S);
-    regular_tet<3, T, EB>(U, eb, lamV, mu2V, F, S);
-    regular_tet<4, T, EB>(U, eb, lamV, mu2V, F, S);
-    regular_tet<5, T, EB>(U, eb, lamV, mu2V, F, S);
+template <typename T, bool EB, bool ST>
+__device__ __forceinline__ void regular_voxel(const T (&U)[8][3], const T (&eb)[3][3], T lamV, T muV,
+                                              T (&F)[8][3], Sym<T> &S) {
+    EdgeSet<T> E, G;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            E.first[a][i] = U[1 << a][i] - U[0][i];
+            E.last[a][i] = U[7][i] - U[7 ^ (1 << a)][i];
+            G.first[a][i] = (T)0;
+            G.last[a][i] = (T)0;
+#pragma unroll
+            for (int b = 0; b < 3; ++b)
+                if (a != b) E.mid[a][b][i] = U[(1 << a) | (1 << b)][i] - U[1 << a][i];
+        }
+    }
+    kuhn_tet_edges<0, 1, 2, T, EB, ST>(E, eb, lamV, muV, G, S);
+    kuhn_tet_edges<0, 2, 1, T, EB, ST>(E, eb, lamV, muV, G, S);
+    kuhn_tet_edges<1, 0, 2, T, EB, ST>(E, eb, lamV, muV, G, S);
+    kuhn_tet_edges<1, 2, 0, T, EB, ST>(E, eb, lamV, muV, G, S);
+    kuhn_tet_edges<2, 0, 1, T, EB, ST>(E, eb, lamV, muV, G, S);
+    kuhn_tet_edges<2, 1, 0, T, EB, ST>(E, eb, lamV, muV, G, S);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        F[0][i] = -(G.first[0][i] + G.first[1][i] + G.first[2][i]);
+        F[7][i] = G.last[0][i] + G.last[1][i] + G.last[2][i];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            // corner e_a: end of first a, start of middle edges ab
+            T fa = G.first[a][i];
+#pragma unroll
+            for (int b = 0; b < 3; ++b)
+                if (b != a) fa -= G.mid[a][b][i];
+            F[1 << a][i] = fa;
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            // corner 7 - e_c = e_a + e_b: end of middle edges ab and ba, start of last c
+            const int a = (c + 1) % 3, b = (c + 2) % 3;
+            F[7 ^ (1 << c)][i] = G.mid[a][b][i] + G.mid[b][a][i] - G.last[c][i];
+        }
+    }
 }
 
 // z-marching tile kernel.  Block = 16 x 16 threads; thread (tx, ty) evaluates the
@@ -104,7 +161,7 @@ __device__ __forceinline__ void regular_voxel(const T (&U)[8][3], const Sym<T> &
 // with the same base when tx, ty >= 1.  Node (a, b) collects corner c of the
 // voxels (a - dx, b - dy): corners 0/4 from its own voxel, 1/5 from the thread
 // at tx - 1, 2/6 from ty - 1 and 3/7 from (tx - 1, ty - 1).
-template <typename T, bool HX, bool EB>
+template <typename T, bool HX, bool EB, bool ST>
 __global__ __launch_bounds__(256) void k_regular(OpArgs<T> A) {
     __shared__ T Dp[3][TC * TC][3];
     __shared__ T FB[TE * TE][18];
@@ -117,10 +174,11 @@ __global__ __launch_bounds__(256) void k_regular(OpArgs<T> A) {
     const int i0 = bx * TO, j0 = by * TO;
     const int k0 = blockIdx.y * A.kz, k1 = min(k0 + A.kz, A.n2);
     const int n0 = A.n0, n1 = A.n1, n2 = A.n2;
-    const int64_t N = A.N;
+    const int64_t N = A.N, plane_sz = (int64_t)n0 * n1;
     const int a = i0 - 1 + tx, b = j0 - 1 + ty;
     // tiles may wrap more than once around small grids: full modulo here, once
     const int aw = ((a % n0) + n0) % n0, bw = ((b % n1) + n1) % n1;
+    const int64_t colv = aw + (int64_t)n0 * bw;
     int64_t colxy[2];
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
@@ -134,41 +192,61 @@ __global__ __launch_bounds__(256) void k_regular(OpArgs<T> A) {
     const T *x = HX ? A.x + (int64_t)r * 3 * N : nullptr;
     T *y = A.y + (int64_t)r * 3 * N;
     const T *cutbuf = A.cutbuf + (int64_t)r * A.nirr * 48;
-    Sym<T> eb = sym_zero<T>();
-    if constexpr (EB) eb = load_ebar<T>(A.ebar + 6 * r);
+    T eb[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    if constexpr (EB) {
+        const Sym<T> e = load_ebar<T>(A.ebar + 6 * r);
+        eb[0][0] = e.xx; eb[1][1] = e.yy; eb[2][2] = e.zz;
+        eb[1][2] = eb[2][1] = e.yz; eb[0][2] = eb[2][0] = e.xz; eb[0][1] = eb[1][0] = e.xy;
+    }
     double acc7[7] = {0, 0, 0, 0, 0, 0, 0};
     double *vs = A.vstress ? A.vstress + (int64_t)r * 6 * N : nullptr;
 
-    auto load_plane = [&](int slot, int kk) {
+    // plane loads go through registers so that the next plane is in flight
+    // while the current layer is computed
+    T pre[2][3];
+    auto fetch_plane = [&](int kk) {
         if constexpr (HX) {
-            const int kw = wrapi(kk, n2);
+            const int64_t off = plane_sz * wrapi(kk, n2);
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                if (tid + 256 * u < TC * TC) {
+                    const int64_t node = colxy[u] + off;
+                    pre[u][0] = x[node];
+                    pre[u][1] = x[N + node];
+                    pre[u][2] = x[2 * N + node];
+                }
+            }
+        }
+    };
+    auto store_plane = [&](int slot) {
+        if constexpr (HX) {
 #pragma unroll
             for (int u = 0; u < 2; ++u) {
                 const int col = tid + 256 * u;
                 if (col < TC * TC) {
-                    const int64_t node = colxy[u] + (int64_t)n0 * n1 * kw;
-                    Dp[slot][col][0] = x[node];
-                    Dp[slot][col][1] = x[N + node];
-                    Dp[slot][col][2] = x[2 * N + node];
+                    Dp[slot][col][0] = pre[u][0];
+                    Dp[slot][col][1] = pre[u][1];
+                    Dp[slot][col][2] = pre[u][2];
                 }
             }
         }
     };
 
-    load_plane(0, k0 - 1);
-    load_plane(1, k0);
+    fetch_plane(k0 - 1);
+    store_plane(0);
+    fetch_plane(k0);
+    store_plane(1);
+    int m = A.vmat[colv + plane_sz * wrapi(k0 - 1, n2)];
     __syncthreads();
 
     T acc[3] = {0, 0, 0};
     for (int s = 0, kl = k0 - 1; kl < k1; ++s, ++kl) {
         const int sb = s % 3, st = (s + 1) % 3;
-        if (kl + 2 <= k1) load_plane((s + 2) % 3, kl + 2);
-        const int kw = wrapi(kl, n2);
-        const int64_t vox = aw + (int64_t)n0 * (bw + (int64_t)n1 * kw);
-        const int m = A.vmat[vox];
+        const bool more = kl + 2 <= k1;
+        if (more) fetch_plane(kl + 2);
+        const int m_next = (kl + 1 < k1) ? A.vmat[colv + plane_sz * wrapi(kl + 1, n2)] : 0;
+        const int64_t vox = colv + plane_sz * wrapi(kl, n2);
         T F[8][3];
-#pragma unroll
-        for (int c = 0; c < 8; ++c) F[c][0] = F[c][1] = F[c][2] = (T)0;
         if (m >= 0) {
             T U[8][3];
 #pragma unroll
@@ -179,10 +257,10 @@ __global__ __launch_bounds__(256) void k_regular(OpArgs<T> A) {
                 for (int i = 0; i < 3; ++i) U[c][i] = HX ? Dp[sl][col][i] : (T)0;
             }
             const T V = (T)(1.0 / 6.0);
-            const T lamV = V * A.lame[2 * m], mu2V = V * (T)2 * A.lame[2 * m + 1];
+            const T lamV = V * A.lame[2 * m], muV = V * A.lame[2 * m + 1];
             Sym<T> S = sym_zero<T>();
-            regular_voxel<T, EB>(U, eb, lamV, mu2V, F, S);
-            if (owner && kl >= k0) {
+            regular_voxel<T, EB, ST>(U, eb, lamV, muV, F, S);
+            if (ST && owner && kl >= k0) {
                 add_sym(acc7, S);
                 if (vs) store_vstress(vs, N, vox, S);
             }
@@ -203,6 +281,7 @@ __global__ __launch_bounds__(256) void k_regular(OpArgs<T> A) {
             FB[tid][12 + i] = F[6][i];
             FB[tid][15 + i] = F[7][i];
         }
+        if (more) store_plane((s + 2) % 3);
         __syncthreads();
         if (owner) {
             T bot[3], top[3];
@@ -212,12 +291,11 @@ __global__ __launch_bounds__(256) void k_regular(OpArgs<T> A) {
                 top[i] = F[4][i] + FB[tid - 1][9 + i] + FB[tid - 16][12 + i] + FB[tid - 17][15 + i];
             }
             if (kl >= k0) {
-                const int64_t node = vox;
                 double dot = 0.0;
 #pragma unroll
                 for (int i = 0; i < 3; ++i) {
                     const T out = A.sign * (acc[i] + bot[i]);
-                    y[i * N + node] = out;
+                    y[i * N + vox] = out;
                     if constexpr (HX) dot += (double)out * (double)Dp[sb][tx + TC * ty][i];
                 }
                 acc7[0] += dot;
@@ -225,6 +303,7 @@ __global__ __launch_bounds__(256) void k_regular(OpArgs<T> A) {
 #pragma unroll
             for (int i = 0; i < 3; ++i) acc[i] = top[i];
         }
+        m = m_next;
         __syncthreads();
     }
     block_sum<7>(acc7, red);
@@ -401,17 +480,17 @@ __global__ __launch_bounds__(256) void k_enriched(OpArgs<T> A) {
     const int64_t jn = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     double acc7[7] = {0, 0, 0, 0, 0, 0, 0};
     if (jn < A.nX) {
-        const int64_t node = A.jlist[jn];
-        const int i = (int)(node % A.n0), j = (int)((node / A.n0) % A.n1), k = (int)(node / ((int64_t)A.n0 * A.n1));
+        // enr_src[j][c] = 8 * (irregular voxel) + corner, or -1: the buffered
+        // corner forces that act on enriched node j
+        const int4 s0 = reinterpret_cast<const int4 *>(A.enr_src)[2 * jn];
+        const int4 s1 = reinterpret_cast<const int4 *>(A.enr_src)[2 * jn + 1];
+        const int src[8] = {s0.x, s0.y, s0.z, s0.w, s1.x, s1.y, s1.z, s1.w};
         const T *cutbuf = A.cutbuf + (int64_t)r * A.nirr * 48;
         T s[3] = {0, 0, 0};
 #pragma unroll
         for (int c = 0; c < 8; ++c) {
-            const int64_t vox = wrapi(i - (c & 1), A.n0) +
-                                (int64_t)A.n0 * (wrapi(j - ((c >> 1) & 1), A.n1) + (int64_t)A.n1 * wrapi(k - (c >> 2), A.n2));
-            const int m = A.vmat[vox];
-            if (m < 0) {
-                const T *cb = cutbuf + (int64_t)(-m - 1) * 48 + 6 * c + 3;
+            if (src[c] >= 0) {
+                const T *cb = cutbuf + (int64_t)src[c] * 6 + 3;
                 s[0] += cb[0]; s[1] += cb[1]; s[2] += cb[2];
             }
         }
@@ -439,13 +518,14 @@ __global__ __launch_bounds__(256) void k_enriched(OpArgs<T> A) {
 template <typename T>
 void launch_operator(xfft_problem *p, Work<T> &w, const Tables<T> &tb, const T *x, const T *xe, T *y, T *ye,
                      bool use_ebar, T sign, int nrhs, const Flags *flags, int parity, double *vstress,
-                     hipStream_t s) {
+                     hipStream_t s, bool stress) {
     const Geometry &g = p->g;
     const SlotLayout &L = p->slots;
     OpArgs<T> A;
     A.x = x; A.xe = xe; A.y = y; A.ye = ye;
     A.ebar = p->ebar; A.sign = sign; A.flags = flags; A.parity = parity;
     A.vmat = p->vmat; A.irr = p->irr; A.irr_j = p->irr_j; A.irr_lab = p->irr_lab; A.jlist = p->jlist;
+    A.enr_src = p->enr_src;
     A.irr_L64 = p->t64.irr_L; A.d0is = tb.d0is; A.lame = tb.lame;
     A.cutbuf = w.cutbuf; A.partial = p->partial; A.nslots = p->nslots;
     A.vstress = vstress;
@@ -466,10 +546,11 @@ void launch_operator(xfft_problem *p, Work<T> &w, const Tables<T> &tb, const T *
         A.slot0 = L.fe0;
         dim3 grid(L.tiles_x * L.tiles_y, L.zchunks, nrhs);
         xfft_prof_mark(p, -1, s);
-        if (hx && use_ebar) k_regular<T, true, true><<<grid, 256, 0, s>>>(A);
-        else if (hx) k_regular<T, true, false><<<grid, 256, 0, s>>>(A);
-        else if (use_ebar) k_regular<T, false, true><<<grid, 256, 0, s>>>(A);
-        else k_regular<T, false, false><<<grid, 256, 0, s>>>(A);
+        if (hx && use_ebar) k_regular<T, true, true, true><<<grid, 256, 0, s>>>(A);
+        else if (hx && stress) k_regular<T, true, false, true><<<grid, 256, 0, s>>>(A);
+        else if (hx) k_regular<T, true, false, false><<<grid, 256, 0, s>>>(A);
+        else if (use_ebar) k_regular<T, false, true, true><<<grid, 256, 0, s>>>(A);
+        else k_regular<T, false, false, false><<<grid, 256, 0, s>>>(A);
         xfft_prof_mark(p, K_REGULAR + (sizeof(T) == 8 ? K_COUNT : 0), s);
     }
     if (g.nX > 0) {
@@ -484,18 +565,21 @@ void launch_operator(xfft_problem *p, Work<T> &w, const Tables<T> &tb, const T *
 
 template void launch_operator<double>(xfft_problem *, Work<double> &, const Tables<double> &, const double *,
                                       const double *, double *, double *, bool, double, int, const Flags *, int,
-                                      double *, hipStream_t);
+                                      double *, hipStream_t, bool);
 template void launch_operator<float>(xfft_problem *, Work<float> &, const Tables<float> &, const float *,
                                      const float *, float *, float *, bool, float, int, const Flags *, int, double *,
-                                     hipStream_t);
+                                     hipStream_t, bool);
 
 SlotLayout slot_layout(const Geometry &g) {
     SlotLayout L{};
     L.tiles_x = (g.n0 + TO - 1) / TO;
     L.tiles_y = (g.n1 + TO - 1) / TO;
     // planes per block: keep at least ~2048 blocks per right-hand side when possible
+    // planes per block: every block recomputes one halo layer, so keep kz >= 8
+    // unless the grid would be left with fewer than ~1024 blocks per load
     int kz = 16;
-    while (kz > 4 && (int64_t)L.tiles_x * L.tiles_y * ((g.n2 + kz - 1) / kz) < 2048) kz /= 2;
+    while (kz > 8 && (int64_t)L.tiles_x * L.tiles_y * ((g.n2 + kz - 1) / kz) < 1024) kz /= 2;
+    while (kz > 4 && (int64_t)L.tiles_x * L.tiles_y * ((g.n2 + kz - 1) / kz) < 256) kz /= 2;
     L.kz = kz;
     L.zchunks = (g.n2 + kz - 1) / kz;
     int at = 0;

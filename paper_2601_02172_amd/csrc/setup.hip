@@ -279,6 +279,19 @@ __global__ void k_d0(int64_t nX, int n0, int n1, int n2, const int32_t *jlist, c
     d0is32[jn] = (float)(1.0 / sqrt(D));
 }
 
+__global__ void k_enr_src(int64_t nX, int n0, int n1, int n2, const int32_t *jlist, const int32_t *vmat,
+                          int32_t *src) {
+    const int64_t jn = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (jn >= nX) return;
+    const int64_t node = jlist[jn];
+    const int i = (int)(node % n0), j = (int)((node / n0) % n1), k = (int)(node / ((int64_t)n0 * n1));
+    for (int c = 0; c < 8; ++c) {
+        const int64_t vox = wrapn(i - (c & 1), n0) + (int64_t)n0 * (wrapn(j - ((c >> 1) & 1), n1) + (int64_t)n1 * wrapn(k - (c >> 2), n2));
+        const int m = vmat[vox];
+        src[jn * 8 + c] = (m < 0) ? (int32_t)(8 * (-(int64_t)m - 1) + c) : -1;
+    }
+}
+
 __global__ void k_fft_tables(int n, double2 *tw64, float2 *tw32, double *half64, float *half32) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n) return;
@@ -398,7 +411,8 @@ int run_setup(xfft_problem *p, const double *L_dev_raw) {
             hipMalloc(&p->t32.irr_L, sizeof(float) * 8 * nirr) != hipSuccess ||
             hipMalloc(&p->d0, sizeof(double) * nX) != hipSuccess ||
             hipMalloc(&p->t64.d0is, sizeof(double) * nX) != hipSuccess ||
-            hipMalloc(&p->t32.d0is, sizeof(float) * nX) != hipSuccess)
+            hipMalloc(&p->t32.d0is, sizeof(float) * nX) != hipSuccess ||
+            hipMalloc(&p->enr_src, sizeof(int32_t) * 8 * nX) != hipSuccess)
             rc = XFFT_ENOMEM_INTERNAL;
     }
     if (!rc && g.nirr > 0) {
@@ -409,6 +423,8 @@ int run_setup(xfft_problem *p, const double *L_dev_raw) {
     if (!rc && g.nX > 0) {
         k_d0<<<(unsigned)((g.nX + tb - 1) / tb), tb, 0, s>>>(g.nX, g.n0, g.n1, g.n2, p->jlist, p->vmat, p->t64.irr_L,
                                                              p->d0_scale, p->d0, p->t64.d0is, p->t32.d0is);
+        k_enr_src<<<(unsigned)((g.nX + tb - 1) / tb), tb, 0, s>>>(g.nX, g.n0, g.n1, g.n2, p->jlist, p->vmat,
+                                                                  p->enr_src);
     }
     if (!rc && hipStreamSynchronize(s) != hipSuccess) rc = XFFT_EDEVICE_INTERNAL;
     if (!rc && hipGetLastError() != hipSuccess) rc = XFFT_EDEVICE_INTERNAL;

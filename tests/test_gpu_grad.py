@@ -1,0 +1,95 @@
+"""GPU gradient of C_eff with respect to the Lame pairs (closed form by Galerkin
+orthogonality) against the oracle's closed form, against central differences
+of the GPU C_eff, and through torch.autograd."""
+
+import numpy as np
+import pytest
+
+import microstructure as ms
+from microstructure.shapes import coated_sphere_levelset
+from oracle.xfem import Discretization
+from oracle.homogenize import effective_stiffness, lame_gradient
+
+pytestmark = pytest.mark.gpu
+
+
+def _case(name):
+    if name == "sphere8":
+        n = (8, 8, 8)
+        L, ph = ms.spheres_levelset(n, [np.array([4.13, 3.93, 4.21])], [2.6])
+        return n, L, ph, np.array([[0.5769231, 0.3846154], [4.0, 4.0]])
+    if name == "coated12":
+        n = (12, 12, 12)
+        L, ph = coated_sphere_levelset(n, np.array([6.1, 5.8, 6.05]), 2.1, 4.4)
+        return n, L, ph, np.array([[0.6, 0.6], [0.48, 0.48], [4.8, 4.8]])
+    if name == "two_spheres16":
+        n = (16, 16, 16)
+        L, ph = ms.spheres_levelset(n, [np.array([4.3, 5.1, 8.2]), np.array([11.7, 10.4, 6.9])], [2.9, 3.4])
+        return n, L, ph, np.array([[0.5769231, 0.3846154], [27.77778, 41.66667], [4.0, 4.0]])
+    raise KeyError(name)
+
+
+def _gpu(name, **kw):
+    from paper_2601_02172_amd import Problem
+    n, L, ph, lame = _case(name)
+    return Problem(n, [float(v) for v in n], L, ph, lame, **kw)
+
+
+@pytest.mark.parametrize("name", ["sphere8", "coated12"])
+def test_gradient_matches_oracle_closed_form(name):
+    n, L, ph, lame = _case(name)
+    d = Discretization(n, tuple(float(v) for v in n), L, ph, lame)
+    C, U, _ = effective_stiffness(d, tol=1e-13)
+    g_or = lame_gradient(d, U, np.eye(6))            # (nphase, 2, 6, 6)
+    with _gpu(name, rtol=1e-12) as p:
+        p.effective_stiffness()
+        W = np.arange(36.0).reshape(6, 6) / 36.0
+        g, dC = p.grad_lame(W)
+    scale = np.abs(g_or).max()
+    assert np.abs(dC - g_or).max() < 1e-9 * scale
+    np.testing.assert_allclose(g, np.einsum("kl,pjkl->pj", W, g_or), rtol=1e-9, atol=1e-12 * scale)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_gradient_matches_central_differences(precision):
+    rng = np.random.default_rng(3)
+    with _gpu("two_spheres16", rtol=1e-12, precision=precision) as p:
+        lame0 = _case("two_spheres16")[3].copy()
+        C0, _ = p.effective_stiffness()
+        Ct = C0 * (1.0 + 0.1 * rng.standard_normal((6, 6)))
+        W = 2.0 * (C0 - Ct)                              # dL/dC of L = ||C - Ct||_F^2
+        g, _ = p.grad_lame(W)
+        for (ph, j) in [(0, 0), (0, 1), (1, 0), (2, 1)]:
+            h = 1e-5 * lame0[ph, j]
+            vals = []
+            for sgn in (+1, -1):
+                lm = lame0.copy()
+                lm[ph, j] += sgn * h
+                p.set_lame(lm)
+                C, _ = p.effective_stiffness()
+                vals.append(np.sum((C - Ct) ** 2))
+            fd = (vals[0] - vals[1]) / (2 * h)
+            assert abs(fd - g[ph, j]) < 1e-5 * abs(g[ph, j]) + 1e-9, (ph, j, fd, g[ph, j])
+        p.set_lame(lame0)
+
+
+def test_gradient_requires_unit_load_solve():
+    from paper_2601_02172_amd import XfftError
+    with _gpu("sphere8") as p:
+        p.solve(np.eye(6)[:1])
+        with pytest.raises(XfftError):
+            p.grad_lame(np.eye(6))
+
+
+def test_autograd_function():
+    import torch
+    from paper_2601_02172_amd.torch_ops import effective_stiffness as ceff
+    with _gpu("sphere8", rtol=1e-12) as p:
+        lame = torch.tensor(_case("sphere8")[3], dtype=torch.float64, requires_grad=True)
+        C = ceff(lame, p)
+        Ct = torch.eye(6, dtype=torch.float64)
+        loss = ((C - Ct) ** 2).sum()
+        loss.backward()
+        W = 2.0 * (C.detach().numpy() - Ct.numpy())
+        g, _ = p.grad_lame(W)
+    np.testing.assert_allclose(lame.grad.numpy(), g, rtol=1e-12)
