@@ -65,7 +65,10 @@ typedef struct {
     double inner_rtol;  /* mixed: residual reduction of each inner FP32 solve (default 1e-4) */
     int32_t batch;      /* 1: all loads of a call iterate together; 0: one load at a time (default 1) */
     int32_t device;     /* HIP device ordinal (default 0) */
-    int32_t check_every;/* host polls convergence every this many iterations (default 8) */
+    int32_t check_every;/* host polls convergence every this many iterations (default 8; rounded up to even) */
+    int32_t use_graph;  /* 1: the check_every iterations between polls are captured once into a hipGraph and
+                           replayed (default 1); 0: launched one by one */
+    int32_t autotune;   /* 1: at the first solve, time the operator's tile depths and keep the fastest (default 1) */
     void *stream;       /* hipStream_t to run on, or NULL for a library-owned stream */
 } xfft_options;
 
@@ -136,8 +139,13 @@ int xfft_set_lame(xfft_problem *p, const double *lame);
  * derivatives.  EINVAL if no suitable solve is stored. */
 int xfft_grad_lame(xfft_problem *p, const double *dL_dC, double *grad, double *dC_out);
 
-/* Solve several problems (uneven grids allowed), each for the six unit Mandel
- * loads, returning c_eff[nprob][6][6]; stats may be NULL or [nprob]. */
+/* Solve several problems (uneven grids allowed, same precision option), each
+ * for the six unit Mandel loads, returning c_eff[nprob][6][6]: the CG
+ * iterations of all problems are captured once as parallel branches of one
+ * hipGraph (fork/join over the problems' streams) and replayed until every load
+ * of every problem has converged; mixed precision refines all problems in
+ * lock step.  The unit-load solutions are kept for xfft_grad_lame.  stats may
+ * be NULL or [nprob] (iters/outer_iters arrays of length 6 each). */
 int xfft_batch_solve(xfft_problem *const *ps, int32_t nprob, double *c_eff, xfft_stats *stats);
 
 /* Step-level entry points (host arrays, voxel units, layout above).

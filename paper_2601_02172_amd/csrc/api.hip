@@ -6,7 +6,9 @@
 
 #include <chrono>
 #include <cmath>
+#include <array>
 #include <cstring>
+#include <map>
 #include <new>
 #include <vector>
 
@@ -133,6 +135,48 @@ void cg_start(xfft_problem *p, Work<T> &w, const Tables<T> &tb, int nrhs, int cr
     launch_scalars(p, SC_INIT_RES, crit, nrhs, 0, nullptr, s, sizeof(T) == 8);
 }
 
+void drop_graph(xfft_problem *p) {
+    if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    p->graph_exec = nullptr;
+    p->graph = nullptr;
+    p->graph_key[0] = -1;
+}
+
+// Enqueue k CG iterations (parities 0, 1, ...; k even) on the problem's stream.
+template <typename T>
+void enqueue_iterations(xfft_problem *p, Work<T> &w, const Tables<T> &tb, int nrhs, int crit, int k) {
+    for (int it = 0; it < k; ++it) cg_iteration<T>(p, w, tb, nrhs, it & 1, crit);
+}
+
+// Capture k iterations into the problem's graph (reused while the launch
+// configuration and the work buffers are unchanged).
+template <typename T>
+int ensure_graph(xfft_problem *p, Work<T> &w, const Tables<T> &tb, int nrhs, int crit, int k) {
+    const int key[4] = {(int)sizeof(T), nrhs, crit, k};
+    const void *ptrs[3] = {w.u, p->partial, w.cutbuf};
+    if (p->graph_exec && std::memcmp(key, p->graph_key, sizeof(key)) == 0 &&
+        std::memcmp(ptrs, p->graph_ptrs, sizeof(ptrs)) == 0)
+        return XFFT_OK;
+    drop_graph(p);
+    hipStream_t s = p->stream;
+    HIP_OK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    enqueue_iterations<T>(p, w, tb, nrhs, crit, k);
+    if (hipStreamEndCapture(s, &p->graph) != hipSuccess) { p->graph = nullptr; return XFFT_EDEVICE; }
+    if (hipGraphInstantiate(&p->graph_exec, p->graph, nullptr, nullptr, 0) != hipSuccess) {
+        drop_graph(p);
+        return XFFT_EDEVICE;
+    }
+    std::memcpy(p->graph_key, key, sizeof(key));
+    std::memcpy(p->graph_ptrs, ptrs, sizeof(ptrs));
+    return XFFT_OK;
+}
+
+int check_period(const xfft_problem *p) {
+    int every = p->check_every > 0 ? p->check_every : 8;
+    return every + (every & 1);          // even: a replay starts at parity 0 again
+}
+
 // Iterate until no right-hand side is active; returns iterations run.
 template <typename T>
 int cg_loop(xfft_problem *p, Work<T> &w, const Tables<T> &tb, int nrhs, int crit, int *rc) {
@@ -142,11 +186,21 @@ int cg_loop(xfft_problem *p, Work<T> &w, const Tables<T> &tb, int nrhs, int crit
     bool any = false;
     for (int r = 0; r < nrhs; ++r) any |= fl[r].active[0] != 0;
     int it = 0;
-    const int every = p->check_every > 0 ? p->check_every : 8;
+    const int every = check_period(p);
+    const bool graph = p->use_graph && !p->prof_on;
+    if (graph && any) {
+        *rc = ensure_graph<T>(p, w, tb, nrhs, crit, every);
+        if (*rc) return 0;
+    }
     while (any && it < p->maxit) {
-        cg_iteration<T>(p, w, tb, nrhs, it & 1, crit);
-        ++it;
-        if (it % every == 0 || it >= p->maxit) {
+        if (graph) {
+            if (hipGraphLaunch(p->graph_exec, p->stream) != hipSuccess) { *rc = XFFT_EDEVICE; return it; }
+            it += every;
+        } else {
+            cg_iteration<T>(p, w, tb, nrhs, it & 1, crit);
+            ++it;
+        }
+        if (graph || it % every == 0 || it >= p->maxit) {
             *rc = read_flags(p, nrhs, fl);
             if (*rc) return it;
             any = false;
@@ -154,6 +208,45 @@ int cg_loop(xfft_problem *p, Work<T> &w, const Tables<T> &tb, int nrhs, int crit
         }
     }
     return it;
+}
+
+// Choose the regular-voxel operator depth (planes per block) by timing the
+// candidates in the solve's launch configuration; results are cached per
+// (grid, precision, loads) for the process.
+template <typename T>
+int autotune_depth(xfft_problem *p, Work<T> &w, const Tables<T> &tb, int nrhs) {
+    static std::map<std::array<int, 5>, int> cache;
+    const std::array<int, 5> key = {p->g.n0, p->g.n1, p->g.n2, (int)sizeof(T), nrhs};
+    auto it = cache.find(key);
+    if (it != cache.end()) {
+        set_depth(p->slots, p->g, it->second);
+        return XFFT_OK;
+    }
+    hipStream_t s = p->stream;
+    HIP_OK(hipMemsetAsync(w.d, 0, sizeof(T) * 3 * p->g.N * nrhs, s));
+    if (p->g.nX) HIP_OK(hipMemsetAsync(w.de, 0, sizeof(T) * 3 * p->g.nX * nrhs, s));
+    hipEvent_t e0, e1;
+    HIP_OK(hipEventCreate(&e0));
+    HIP_OK(hipEventCreate(&e1));
+    int best = p->slots.kz;
+    float best_ms = 1e30f;
+    for (int kz : {4, 8, 16}) {
+        if (kz > p->g.n2) continue;
+        set_depth(p->slots, p->g, kz);
+        launch_operator<T>(p, w, tb, w.d, w.de, w.z, w.ze, false, (T)1, nrhs, nullptr, 0, nullptr, s, false);
+        (void)hipEventRecord(e0, s);
+        for (int rep = 0; rep < 5; ++rep)
+            launch_operator<T>(p, w, tb, w.d, w.de, w.z, w.ze, false, (T)1, nrhs, nullptr, 0, nullptr, s, false);
+        (void)hipEventRecord(e1, s);
+        float ms = 0.0f;
+        if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) break;
+        if (ms < best_ms) { best_ms = ms; best = kz; }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    set_depth(p->slots, p->g, best);
+    cache[key] = best;
+    return XFFT_OK;
 }
 
 // Average stress (Mandel) of the FP64 iterate in w64.u for every rhs; optional voxel stress.
@@ -190,6 +283,13 @@ int solve_block(xfft_problem *p, int nrhs, const double *ebar_host, std::vector<
     }
     rc = ensure_state(p, nrhs);
     if (rc) return rc;
+    if (p->autotune && !p->tuned) {
+        rc = (p->precision == XFFT_MIXED) ? autotune_depth<float>(p, p->w32, p->t32, nrhs)
+                                          : autotune_depth<double>(p, p->w64, p->t64, nrhs);
+        if (rc) return rc;
+        p->tuned = true;
+        drop_graph(p);
+    }
     rc = reset_state(p, nrhs, ebar_host);
     if (rc) return rc;
     hipStream_t s = p->stream;
@@ -493,6 +593,8 @@ void xfft_default_options(xfft_options *opt) {
     opt->batch = 1;
     opt->device = 0;
     opt->check_every = 8;
+    opt->use_graph = 1;
+    opt->autotune = 1;
     opt->stream = nullptr;
 }
 
@@ -523,6 +625,7 @@ void xfft_destroy(xfft_problem *p) {
         if (p->t64.half[a]) (void)hipFree(p->t64.half[a]);
         if (p->t32.half[a]) (void)hipFree(p->t32.half[a]);
     }
+    drop_graph(p);
     free_work(p->w64);
     free_work(p->w32);
     for (hipEvent_t e : p->prof_pool) (void)hipEventDestroy(e);
@@ -566,6 +669,8 @@ int xfft_setup(const int32_t n[3], const double len[3], const double *levelset, 
     for (int a = 0; a < 3; ++a) p->len[a] = len[a];
     p->rtol = opt.rtol; p->snap_eps = opt.snap_eps; p->d0_scale = opt.d0_scale; p->inner_rtol = opt.inner_rtol;
     p->maxit = opt.maxit; p->precision = opt.precision; p->batch = opt.batch; p->check_every = opt.check_every;
+    p->use_graph = opt.use_graph != 0;
+    p->autotune = opt.autotune != 0;
     if (opt.stream) {
         p->stream = (hipStream_t)opt.stream;
     } else {
@@ -796,13 +901,177 @@ int xfft_grad_lame(xfft_problem *p, const double *dL_dC, double *grad, double *d
 
 int xfft_batch_solve(xfft_problem *const *ps, int32_t nprob, double *c_eff, xfft_stats *stats) {
     if (!ps || nprob < 1 || !c_eff) return XFFT_EINVAL;
+    for (int i = 0; i < nprob; ++i)
+        if (!ps[i] || ps[i]->precision != ps[0]->precision || ps[i]->device != ps[0]->device) return XFFT_EINVAL;
+    HIP_OK(hipSetDevice(ps[0]->device));
+    const double t0 = now_s();
+    const int nl = 6;
     double E[36];
     for (int k = 0; k < 36; ++k) E[k] = (k % 7 == 0) ? 1.0 : 0.0;
-    int status = XFFT_OK;
+    const bool mixed = ps[0]->precision == XFFT_MIXED;
+    // prepare every problem on its own stream
     for (int i = 0; i < nprob; ++i) {
-        int rc = xfft_solve(ps[i], 6, E, nullptr, nullptr, nullptr, c_eff + 36 * i, stats ? stats + i : nullptr);
-        if (rc < 0) return rc;
-        if (rc == XFFT_NOT_CONVERGED) status = rc;
+        xfft_problem *p = ps[i];
+        int rc = alloc_work<double>(p, p->w64, nl);
+        if (!rc && mixed) rc = alloc_work<float>(p, p->w32, nl);
+        if (!rc) rc = ensure_state(p, nl);
+        if (!rc && p->autotune && !p->tuned) {
+            rc = mixed ? autotune_depth<float>(p, p->w32, p->t32, nl) : autotune_depth<double>(p, p->w64, p->t64, nl);
+            p->tuned = true;
+        }
+        if (!rc) rc = reset_state(p, nl, E);
+        if (rc) return rc;
+        HIP_OK(hipMemsetAsync(p->w64.u, 0, sizeof(double) * 3 * p->g.N * nl, p->stream));
+        if (p->g.nX) HIP_OK(hipMemsetAsync(p->w64.ue, 0, sizeof(double) * 3 * p->g.nX * nl, p->stream));
+        p->sol_unit_basis = false;
+    }
+    // one graph: every problem's iterations as a branch between a fork and a join
+    const int every = check_period(ps[0]);
+    const int crit = mixed ? 1 : 0;
+    hipStream_t master = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<hipEvent_t> ev(nprob + 1, nullptr);
+    int rc = XFFT_OK;
+    auto cleanup = [&]() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        for (hipEvent_t e : ev)
+            if (e) (void)hipEventDestroy(e);
+        if (master) (void)hipStreamDestroy(master);
+    };
+    if (hipStreamCreate(&master) != hipSuccess) return XFFT_EDEVICE;
+    for (auto &e : ev)
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) { cleanup(); return XFFT_EDEVICE; }
+    for (int i = 0; i < nprob; ++i)
+        if (hipStreamSynchronize(ps[i]->stream) != hipSuccess) { cleanup(); return XFFT_EDEVICE; }
+    if (hipStreamBeginCapture(master, hipStreamCaptureModeThreadLocal) != hipSuccess) { cleanup(); return XFFT_EDEVICE; }
+    bool cap_ok = hipEventRecord(ev[nprob], master) == hipSuccess;
+    for (int i = 0; i < nprob && cap_ok; ++i) {
+        xfft_problem *p = ps[i];
+        cap_ok = hipStreamWaitEvent(p->stream, ev[nprob], 0) == hipSuccess;
+        if (!cap_ok) break;
+        if (mixed) enqueue_iterations<float>(p, p->w32, p->t32, nl, crit, every);
+        else enqueue_iterations<double>(p, p->w64, p->t64, nl, crit, every);
+        cap_ok = hipEventRecord(ev[i], p->stream) == hipSuccess && hipStreamWaitEvent(master, ev[i], 0) == hipSuccess;
+    }
+    if (hipStreamEndCapture(master, &graph) != hipSuccess || !cap_ok ||
+        hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+        cleanup();
+        return XFFT_EDEVICE;
+    }
+    auto poll = [&](std::vector<std::vector<Flags>> &fl) -> int {
+        for (int i = 0; i < nprob; ++i)
+            HIP_OK(hipMemcpyAsync(ps[i]->host_flags, ps[i]->flags, sizeof(Flags) * nl, hipMemcpyDeviceToHost, master));
+        HIP_OK(hipStreamSynchronize(master));
+        for (int i = 0; i < nprob; ++i)
+            fl[i].assign(reinterpret_cast<Flags *>(ps[i]->host_flags), reinterpret_cast<Flags *>(ps[i]->host_flags) + nl);
+        return XFFT_OK;
+    };
+    std::vector<std::vector<Flags>> fl(nprob);
+    auto run_inner = [&]() -> int {
+        int it = 0;
+        for (int i = 0; i < nprob; ++i) HIP_OK(hipStreamSynchronize(ps[i]->stream));
+        int r = poll(fl);
+        if (r) return r;
+        const int maxit = ps[0]->maxit;
+        while (it < maxit) {
+            bool any = false;
+            for (int i = 0; i < nprob; ++i)
+                for (int q = 0; q < nl; ++q) any |= fl[i][q].active[0] != 0;
+            if (!any) break;
+            HIP_OK(hipGraphLaunch(exec, master));
+            it += every;
+            r = poll(fl);
+            if (r) return r;
+        }
+        return XFFT_OK;
+    };
+    std::vector<int> outer(nprob * nl, 0);
+    if (!mixed) {
+        for (int i = 0; i < nprob; ++i) {
+            xfft_problem *p = ps[i];
+            Work<double> &w = p->w64;
+            launch_operator<double>(p, w, p->t64, nullptr, nullptr, w.f, w.fe, true, -1.0, nl, nullptr, 0, nullptr,
+                                    p->stream);
+            launch_scalars(p, SC_INIT_SIGMA, 0, nl, 0, nullptr, p->stream, true);
+            cg_start<double>(p, w, p->t64, nl, 0);
+        }
+        rc = run_inner();
+    } else {
+        for (int o = 0; o < 60 && !rc; ++o) {
+            for (int i = 0; i < nprob; ++i) {
+                xfft_problem *p = ps[i];
+                Work<double> &w = p->w64;
+                launch_operator<double>(p, w, p->t64, o == 0 ? nullptr : w.u, w.ue, w.f, w.fe, true, -1.0, nl,
+                                        nullptr, 0, nullptr, p->stream);
+                launch_scalars(p, SC_INIT_SIGMA, 0, nl, 0, nullptr, p->stream, true);
+                launch_round_to_float(p, nl, p->stream);
+                cg_start<float>(p, p->w32, p->t32, nl, 0);
+            }
+            for (int i = 0; i < nprob; ++i)
+                if (hipStreamSynchronize(ps[i]->stream) != hipSuccess) rc = XFFT_EDEVICE;
+            if (rc) break;
+            rc = poll(fl);
+            if (rc) break;
+            bool all_done = true;
+            for (int i = 0; i < nprob; ++i)
+                for (int q = 0; q < nl; ++q)
+                    if (!fl[i][q].pad[0]) { all_done = false; outer[i * nl + q] = o + 1; }
+            if (all_done) break;
+            rc = run_inner();
+            if (rc) break;
+            for (int i = 0; i < nprob; ++i) launch_accumulate_correction(ps[i], nl, ps[i]->stream);
+        }
+    }
+    cleanup();
+    if (rc) return rc;
+    int status = XFFT_OK;
+    for (int i = 0; i < nprob && !rc; ++i) {
+        xfft_problem *p = ps[i];
+        std::vector<Flags> f;
+        rc = read_flags(p, nl, f);
+        if (rc) break;
+        std::vector<double> avg(6 * nl);
+        rc = final_outputs(p, nl, avg.data(), nullptr);
+        if (rc) break;
+        for (int k = 0; k < 6; ++k)
+            for (int q = 0; q < 6; ++q) c_eff[36 * i + 6 * q + k] = avg[6 * k + q];
+        for (int q = 0; q < nl; ++q) {
+            const bool done = mixed ? f[q].pad[0] != 0 : f[q].conv != 0;
+            if (f[q].breakdown) status = XFFT_EBREAKDOWN;
+            else if (!done && status == XFFT_OK) status = XFFT_NOT_CONVERGED;
+        }
+        // keep the unit-load solutions for xfft_grad_lame
+        if (!p->sol_u) {
+            if (hipMalloc(&p->sol_u, sizeof(double) * 6 * 3 * p->g.N) != hipSuccess ||
+                hipMalloc(&p->sol_ue, sizeof(double) * 6 * 3 * (p->g.nX > 0 ? p->g.nX : 1)) != hipSuccess)
+                return XFFT_ENOMEM;
+        }
+        HIP_OK(hipMemcpyAsync(p->sol_u, p->w64.u, sizeof(double) * 18 * p->g.N, hipMemcpyDeviceToDevice, p->stream));
+        if (p->g.nX)
+            HIP_OK(hipMemcpyAsync(p->sol_ue, p->w64.ue, sizeof(double) * 18 * p->g.nX, hipMemcpyDeviceToDevice,
+                                  p->stream));
+        HIP_OK(hipStreamSynchronize(p->stream));
+        p->sol_unit_basis = true;
+        if (stats) {
+            xfft_stats &st = stats[i];
+            for (int q = 0; q < nl; ++q) {
+                if (st.iters) st.iters[q] = f[q].iters;
+                if (st.outer_iters) st.outer_iters[q] = outer[i * nl + q];
+            }
+            st.n_enriched = p->g.nX;
+            st.n_irregular_voxels = p->g.nirr;
+            st.n_cut_elements = p->n_cut_elements;
+            st.n_multilabel = p->n_multilabel;
+            st.seconds_setup = p->seconds_setup;
+        }
+    }
+    if (rc) return rc;
+    const double dt = now_s() - t0;
+    for (int i = 0; i < nprob; ++i) {
+        ps[i]->seconds_solve = dt;
+        if (stats) stats[i].seconds_solve = dt;
     }
     return status;
 }

@@ -179,9 +179,9 @@ void launch_scalars(xfft_problem *p, int op, int crit, int nrhs, int parity, dou
     const SlotLayout &L = p->slots;
     if (op == SC_INIT_SIGMA || op == SC_ALPHA || op == SC_SUM_ONLY) {
         A.s0 = L.fe0;
-        A.n = L.fe_n + L.cut_n + L.enr_n;
-        A.s1 = 0;
-        A.n1 = 0;
+        A.n = L.fe_n;
+        A.s1 = L.cut0;
+        A.n1 = L.cut_n + L.enr_n;
     } else {
         A.s0 = L.grn0;
         A.n = fp64 ? green_blocks<double>(p->g) : green_blocks<float>(p->g);

@@ -114,7 +114,8 @@ template <typename T> struct Work {
 
 // Partial-sum slot layout per right-hand side.
 struct SlotLayout {
-    int fe0, fe_n;      // regular-voxel operator blocks
+    int fe0, fe_n;      // regular-voxel operator blocks at the current depth kz
+    int fe_cap;         // slots reserved for the regular-voxel blocks (depth 4)
     int cut0, cut_n;    // irregular-voxel blocks
     int enr0, enr_n;    // enriched gather blocks
     int grn0, grn_n;    // Green (z pass) blocks
@@ -193,6 +194,14 @@ struct xfft_problem {
     int sol_nload = 0;
     bool sol_unit_basis = false;
     double seconds_setup = 0.0, seconds_solve = 0.0;
+    // captured CG iterations (replayed as one hipGraph launch)
+    bool use_graph = true;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    int graph_key[4] = {-1, -1, -1, -1};  // precision bytes, nrhs, criterion, iterations
+    const void *graph_ptrs[3] = {nullptr, nullptr, nullptr};
+    bool autotune = true;
+    bool tuned = false;
     // profiling hook: events recorded before (id -1) and after (kernel id) every launch
     bool prof_on = false;
     std::vector<hipEvent_t> prof_pool;   // reusable events

@@ -6,6 +6,8 @@
 namespace xfft {
 
 SlotLayout slot_layout(const Geometry &g);
+// regular-voxel operator depth (planes per block); kz in {4, 8, 16}
+void set_depth(SlotLayout &L, const Geometry &g, int kz);
 int green_slots(const Geometry &g);
 template <typename T> int green_blocks(const Geometry &g);
 

@@ -570,20 +570,27 @@ template void launch_operator<float>(xfft_problem *, Work<float> &, const Tables
                                      const float *, float *, float *, bool, float, int, const Flags *, int, double *,
                                      hipStream_t, bool);
 
+void set_depth(SlotLayout &L, const Geometry &g, int kz) {
+    L.kz = kz;
+    L.zchunks = (g.n2 + kz - 1) / kz;
+    L.fe_n = L.tiles_x * L.tiles_y * L.zchunks;
+}
+
 SlotLayout slot_layout(const Geometry &g) {
     SlotLayout L{};
     L.tiles_x = (g.n0 + TO - 1) / TO;
     L.tiles_y = (g.n1 + TO - 1) / TO;
-    // planes per block: keep at least ~2048 blocks per right-hand side when possible
     // planes per block: every block recomputes one halo layer, so keep kz >= 8
-    // unless the grid would be left with fewer than ~1024 blocks per load
+    // unless the grid would be left with fewer than ~1024 blocks per load (the
+    // autotuner may change it later, within the reserved slots of depth 4)
     int kz = 16;
     while (kz > 8 && (int64_t)L.tiles_x * L.tiles_y * ((g.n2 + kz - 1) / kz) < 1024) kz /= 2;
     while (kz > 4 && (int64_t)L.tiles_x * L.tiles_y * ((g.n2 + kz - 1) / kz) < 256) kz /= 2;
-    L.kz = kz;
-    L.zchunks = (g.n2 + kz - 1) / kz;
     int at = 0;
-    L.fe0 = at; L.fe_n = L.tiles_x * L.tiles_y * L.zchunks; at += L.fe_n;
+    L.fe0 = at;
+    L.fe_cap = L.tiles_x * L.tiles_y * ((g.n2 + 3) / 4);
+    at += L.fe_cap;
+    set_depth(L, g, kz);
     L.cut0 = at; L.cut_n = (int)((g.nirr + 127) / 128); at += L.cut_n;
     L.enr0 = at; L.enr_n = (int)((g.nX + 255) / 256); at += L.enr_n;
     L.grn0 = at; L.grn_n = 0; // filled by the FFT planner

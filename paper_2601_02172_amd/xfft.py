@@ -37,6 +37,8 @@ class Options(ctypes.Structure):
         ("batch", ctypes.c_int32),
         ("device", ctypes.c_int32),
         ("check_every", ctypes.c_int32),
+        ("use_graph", ctypes.c_int32),
+        ("autotune", ctypes.c_int32),
         ("stream", ctypes.c_void_p),
     ]
 
@@ -137,7 +139,7 @@ class Problem:
 
     def __init__(self, n, length, levelset, phase, lame, *, rtol=1e-10, maxit=20000, precision="fp64",
                  snap_eps=1e-6, d0_scale=1.0, inner_rtol=1e-4, batch=True, device=0, check_every=8,
-                 stream=None):
+                 use_graph=True, autotune=True, stream=None):
         lib = _lib()
         self._h = None
         n = np.ascontiguousarray(n, dtype=np.int32)
@@ -154,6 +156,7 @@ class Problem:
         o.rtol, o.maxit, o.precision = rtol, maxit, _PREC[precision]
         o.snap_eps, o.d0_scale, o.inner_rtol = snap_eps, d0_scale, inner_rtol
         o.batch, o.device, o.check_every = int(bool(batch)), device, check_every
+        o.use_graph, o.autotune = int(bool(use_graph)), int(bool(autotune))
         o.stream = stream
         h = ctypes.c_void_p()
         _check(lib.xfft_setup(_ip(n), _dp(length), _dp(L), _ip(ph), self.nphase, _dp(lame), ctypes.byref(o),
@@ -295,10 +298,18 @@ class Problem:
         return out
 
 
-def batch_effective_stiffness(problems):
+def batch_effective_stiffness(problems, with_stats=False):
     """C_eff of several problems (uneven grids allowed): array (nprob, 6, 6)."""
     arr = (ctypes.c_void_p * len(problems))(*[p._h.value for p in problems])
     C = np.zeros((len(problems), 6, 6))
-    rc = _lib().xfft_batch_solve(arr, len(problems), _dp(C), None)
+    iters = np.zeros((len(problems), 6), dtype=np.int32)
+    outer = np.zeros((len(problems), 6), dtype=np.int32)
+    st = (Stats * len(problems))()
+    for i in range(len(problems)):
+        st[i].iters = iters[i].ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        st[i].outer_iters = outer[i].ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+    rc = _lib().xfft_batch_solve(arr, len(problems), _dp(C), st)
     _check(rc, "xfft_batch_solve", allow_not_converged=True)
+    if with_stats:
+        return C, dict(iters=iters, outer_iters=outer, converged=(rc == XFFT_OK), seconds_solve=st[0].seconds_solve)
     return C
