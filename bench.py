@@ -100,6 +100,7 @@ def main():
     ap.add_argument("--inner-rtol", type=float, default=1e-4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--workload", default="spheres128", choices=["spheres128", "ellipsoids256"])
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -111,7 +112,16 @@ def main():
     from paper_2601_02172_amd import Problem
 
     torch.cuda.init()
-    cfg = ms.config_spheres128()
+    t_gen = time.perf_counter()
+    if args.workload == "spheres128":
+        cfg = ms.config_spheres128()
+        wl_desc = "spheres128: 128^3, 40 RSA spheres r~U[0.06,0.1]L, contrast 10, 6 unit loads"
+    else:
+        log("generating the 256^3 ellipsoid microstructure (about a minute on the host)")
+        cfg = ms.config_ellipsoids()
+        wl_desc = ("ellipsoids256: 256^3, 200 random prolate spheroids (aspect 3), vf 0.20, "
+                   "per-inclusion lognormal Lame pairs, 6 unit loads")
+    log(f"inputs ready in {time.perf_counter() - t_gen:.1f}s")
     E = np.eye(6)
 
     def make(precision, batch):
@@ -158,7 +168,7 @@ def main():
         log(f"fp64 plain: {fp64['ms_per_step']:.1f} ms/step, iters {fp64['iters']}")
 
     # accuracy of both paths against a reference C_eff
-    golden = os.path.join(ROOT, "tests", "golden", "oracle_spheres128.json")
+    golden = os.path.join(ROOT, "tests", "golden", f"oracle_{args.workload}.json")
     if os.path.exists(golden):
         C_ref = np.array(json.load(open(golden))["c_eff"])
         ref_kind = "oracle"
@@ -199,8 +209,24 @@ def main():
                for k, v in prof.items()}
     region_summary = {f"{k[0]}/{k[1]}": [round(v[0], 5), v[1]] for k, v in region.items() if v[1]}
     log(f"dominant kernel {dom}: {dom_ms:.4f} ms, {achieved:.0f} GB/s")
+    grad_info = None
+    if args.workload == "ellipsoids256":
+        # loss ||C_eff - C_t||_F^2 with C_t = C_eff at the median moduli; gradient over all Lame pairs
+        lame_med = cfg["lame"].copy()
+        lame_med[1:] = np.median(cfg["lame"][1:], axis=0)
+        pm.set_lame(lame_med)
+        C_t = pm.effective_stiffness()[0]
+        pm.set_lame(cfg["lame"])
+        C_now = pm.effective_stiffness()[0]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g, _ = pm.grad_lame(2.0 * (C_now - C_t))
+        t_grad = time.perf_counter() - t0
+        grad_info = dict(parameters=int(g.size), seconds=round(t_grad, 4), loss=float(np.sum((C_now - C_t) ** 2)),
+                         grad_norm=float(np.linalg.norm(g)))
+        log(f"gradient over {g.size} Lame parameters in {t_grad:.3f}s")
     cpu = None
-    if not args.no_cpu_baseline and fp64:
+    if not args.no_cpu_baseline and fp64 and args.workload == "spheres128":
         log("timing the CPU oracle on a bounded sample")
         cpu = cpu_baseline(cfg, fp64["iters"])
         log(f"cpu baseline {cpu['value']:.3e} solves/s")
@@ -218,7 +244,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f32 (FP64 refinement)",
         "data": "synthetic",
-        "config": {"workload": "spheres128: 128^3, 40 RSA spheres r~U[0.06,0.1]L, contrast 10, 6 unit loads",
+        "config": {"workload": wl_desc,
                    "rtol": args.rtol, "inner_rtol": args.inner_rtol, "precision": "mixed", "batched_loads": 6,
                    "n_enriched": lay["nX"], "n_irregular_voxels": lay["n_irregular_voxels"],
                    "vf": cfg["info"]["vf"]},
@@ -231,6 +257,7 @@ def main():
         "setup_seconds": round(setup_s, 4),
         "kernels": kernels,
         "timed_region_kernels": region_summary,
+        "loss_gradient": grad_info,
     }
     print(json.dumps(out))
 

@@ -118,7 +118,7 @@ def _ellipsoid_distance(p, axes):
     inside = np.sum((q / a) ** 2, axis=1) < 1.0
     lo = np.where(inside, -a2.min() * (1.0 - 1e-15), 0.0)
     hi = np.where(inside, 0.0, np.sqrt(np.sum(q * q, axis=1)) * a.max() + a2.max())
-    for _ in range(200):
+    for _ in range(80):          # the bracket shrinks below double resolution well before
         t = 0.5 * (lo + hi)
         F = np.sum((a[None, :] * q / (t[:, None] + a2[None, :])) ** 2, axis=1) - 1.0
         pos = F > 0.0
@@ -130,29 +130,62 @@ def _ellipsoid_distance(p, axes):
     return np.where(inside, -d, d)
 
 
+def _periodic_box(n, c, reach):
+    """Wrapped index ranges and periodic offsets of the box |x - c| <= reach (per axis)."""
+    idx, off = [], []
+    for a in range(3):
+        lo = int(np.floor(c[a] - reach))
+        hi = int(np.ceil(c[a] + reach))
+        if hi - lo + 1 >= n[a]:
+            lo, hi = 0, n[a] - 1
+            pos = np.arange(n[a])
+            d = periodic_delta(pos.astype(np.float64), c[a], n[a])
+        else:
+            pos = np.arange(lo, hi + 1)
+            d = pos - c[a]
+            pos = np.mod(pos, n[a])
+        idx.append(pos)
+        off.append(d.astype(np.float64))
+    return idx, off
+
+
+def _box_local(off, R):
+    """Local (rotated) coordinates of all box points: array (nz, ny, nx, 3)."""
+    dx, dy, dz = off
+    g = np.stack(np.broadcast_arrays(dx[None, None, :], dy[None, :, None], dz[:, None, None]), axis=-1)
+    return g @ np.asarray(R)
+
+
 def ellipsoids_levelset(n, centers, axes, rotations, clamp=3.0):
     """Signed distance (clamped to +-clamp) to the nearest of several ellipsoids.
 
-    ``rotations[i]`` maps local to global coordinates.  Nodes farther than
-    ``clamp`` from every surface get L = +clamp (matrix) or -clamp (inside).
+    ``rotations[i]`` maps local to global coordinates.  Only nodes within a
+    shell of +-clamp around each surface need the exact distance (root find);
+    deeper nodes get -clamp (inside) and farther ones stay at +clamp.
     """
-    x, y, z = node_coords(n)
-    L = np.full(x.shape, clamp)
-    phase = np.zeros(x.shape, dtype=np.int32)
+    L3 = np.full((n[2], n[1], n[0]), clamp)
+    P3 = np.zeros((n[2], n[1], n[0]), dtype=np.int32)
     for idx, (c, ax, R) in enumerate(zip(centers, axes, rotations)):
+        ax = np.asarray(ax, dtype=np.float64)
         reach = float(np.max(ax)) + clamp + 1.0
-        dx = periodic_delta(x, c[0], n[0])
-        dy = periodic_delta(y, c[1], n[1])
-        dz = periodic_delta(z, c[2], n[2])
-        near = (np.abs(dx) <= reach) & (np.abs(dy) <= reach) & (np.abs(dz) <= reach)
-        ids = np.nonzero(near)[0]
-        g = np.stack([dx[ids], dy[ids], dz[ids]], axis=1)
-        loc = g @ np.asarray(R)  # row-vector form of R^T g
-        d = np.clip(_ellipsoid_distance(loc, ax), -clamp, clamp)
-        better = d < L[ids]
-        L[ids] = np.where(better, d, L[ids])
-        phase[ids] = np.where(better & (d < 0.0), idx + 1, np.where(better, 0, phase[ids]))
-    return L.astype(np.float64), phase.astype(np.int32)
+        (ix, iy, iz), off = _periodic_box(n, c, reach)
+        loc = _box_local(off, R)
+        q_out = np.sum((loc / (ax + clamp)) ** 2, axis=-1)
+        inner = np.maximum(ax - clamp, 1e-6)
+        q_in = np.sum((loc / inner) ** 2, axis=-1)
+        d = np.full(q_out.shape, clamp)
+        deep = (q_in <= 1.0) & np.all(ax > clamp)
+        d[deep] = -clamp
+        shell = (q_out <= 1.0) & ~deep
+        if np.any(shell):
+            d[shell] = np.clip(_ellipsoid_distance(loc[shell], ax), -clamp, clamp)
+        sub = np.ix_(iz, iy, ix)
+        cur = L3[sub]
+        better = d < cur
+        L3[sub] = np.where(better, d, cur)
+        ph = P3[sub]
+        P3[sub] = np.where(better & (d < 0.0), idx + 1, np.where(better, 0, ph))
+    return L3.ravel().astype(np.float64), P3.ravel().astype(np.int32)
 
 
 def _random_rotation(rng):
@@ -173,8 +206,7 @@ def rsa_ellipsoids(n, count, axes, gap, rng, max_tries=20000):
     Overlap is tested on the node raster: every candidate's ellipsoid inflated
     by ``gap / 2`` must not cover a node already covered by an accepted one.
     """
-    x, y, z = node_coords(n)
-    occupied = np.zeros(x.shape, dtype=bool)
+    occupied = np.zeros((n[2], n[1], n[0]), dtype=bool)
     ax_inf = np.asarray(axes, dtype=np.float64) + 0.5 * gap
     reach = float(np.max(ax_inf)) + 1.0
     centers, rots = [], []
@@ -185,16 +217,20 @@ def rsa_ellipsoids(n, count, axes, gap, rng, max_tries=20000):
         tries += 1
         c = rng.uniform(0.0, 1.0, 3) * np.asarray(n, dtype=np.float64)
         R = _random_rotation(rng)
-        dx = periodic_delta(x, c[0], n[0])
-        dy = periodic_delta(y, c[1], n[1])
-        dz = periodic_delta(z, c[2], n[2])
-        near = (np.abs(dx) <= reach) & (np.abs(dy) <= reach) & (np.abs(dz) <= reach)
-        ids = np.nonzero(near)[0]
-        loc = np.stack([dx[ids], dy[ids], dz[ids]], axis=1) @ R
-        cover = np.sum((loc / ax_inf[None, :]) ** 2, axis=1) <= 1.0
-        if np.any(occupied[ids[cover]]):
+        if centers:
+            # both inflated ellipsoids contain the ball of their smallest axis:
+            # closer centres certainly overlap (cheap rejection before the raster test)
+            dc = periodic_delta(np.asarray(centers), c[None, :], np.asarray(n, dtype=np.float64)[None, :])
+            if np.min(np.sum(dc * dc, axis=1)) < (2.0 * float(np.min(ax_inf))) ** 2:
+                continue
+        (ix, iy, iz), off = _periodic_box(n, c, reach)
+        loc = _box_local(off, R)
+        cover = np.sum((loc / ax_inf) ** 2, axis=-1) <= 1.0
+        sub = np.ix_(iz, iy, ix)
+        occ = occupied[sub]
+        if np.any(occ & cover):
             continue
-        occupied[ids[cover]] = True
+        occupied[sub] = occ | cover
         centers.append(c)
         rots.append(R)
     return np.array(centers), np.array(rots)

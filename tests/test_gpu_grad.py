@@ -93,3 +93,26 @@ def test_autograd_function():
         W = 2.0 * (C.detach().numpy() - Ct.numpy())
         g, _ = p.grad_lame(W)
     np.testing.assert_allclose(lame.grad.numpy(), g, rtol=1e-12)
+
+
+def test_ellipsoid_rve_gradient_central_differences():
+    # randomly oriented prolate spheroids with per-inclusion Lame pairs (64^3):
+    # five parameters -- matrix lambda and mu, and three of two inclusions
+    from paper_2601_02172_amd import Problem
+    cfg = ms.config_ellipsoids(N=64, count=25, b_frac=0.06, seed=11)
+    lame0 = cfg["lame"].copy()
+    with Problem(cfg["n"], cfg["length"], cfg["L"], cfg["phase"], lame0, rtol=1e-12) as p:
+        C0, _ = p.effective_stiffness()
+        Ct = C0 * 0.97
+        g, _ = p.grad_lame(2.0 * (C0 - Ct))
+        assert g.shape == (26, 2)
+        for (ph, j) in [(0, 0), (0, 1), (1, 0), (1, 1), (7, 1)]:
+            h = 1e-5 * lame0[ph, j]
+            vals = []
+            for sgn in (+1, -1):
+                lm = lame0.copy()
+                lm[ph, j] += sgn * h
+                p.set_lame(lm)
+                vals.append(np.sum((p.effective_stiffness()[0] - Ct) ** 2))
+            fd = (vals[0] - vals[1]) / (2 * h)
+            assert abs(fd - g[ph, j]) < 1e-5 * abs(g[ph, j]) + 1e-9 * np.abs(g).max(), (ph, j, fd, g[ph, j])
