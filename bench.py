@@ -30,6 +30,20 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# copy-like calibration kernel for the HBM byte counters: elementwise negation of
+# a float32 buffer reads and writes exactly COPY_BYTES each
+COPY_BYTES = 256 << 20
+# kernel classes -> substrings of the HIP kernel names
+KERNEL_NAMES = {
+    "regular_voxels": ["k_regular<"],
+    "irregular_voxels": ["k_irregular<"],
+    "enriched_gather": ["k_enriched<"],
+    "fft_x_forward": ["k_fft_plane_fwd<", "k_fft_x_fwd<"],
+    "fft_y_forward": ["k_fft_y<{t}, false>"],
+    "fft_z_green": ["k_fft_z_t<", "k_fft_z_green<"],
+    "fft_y_inverse": ["k_fft_y<{t}, true>"],
+    "fft_x_inverse": ["k_fft_plane_inv<", "k_fft_x_inv<"],
+}
 
 
 def log(msg):
@@ -60,6 +74,84 @@ def algorithmic_bytes(g, s, nrhs):
         "scalars": 0,
     }
     return {k: v * nrhs for k, v in per.items()}
+
+
+def source_digest():
+    """SHA-256 over the HIP sources and the C header (the counters belong to this code)."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2601_02172_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(name.encode() + b"\0" + f.read())
+    with open(os.path.join(ROOT, "include", "xfft.h"), "rb") as f:
+        h.update(f.read())
+    return h.hexdigest()
+
+
+def _kernel_class(name):
+    prec = "fp32" if "<float" in name else "fp64" if "<double" in name else None
+    if prec is None:
+        return None
+    t = "float" if prec == "fp32" else "double"
+    for k, pats in KERNEL_NAMES.items():
+        if any(p.format(t=t) in name for p in pats):
+            return k, prec
+    return None
+
+
+def pmc_summary(fetch_csv, write_csv):
+    """Mean HBM bytes per dispatch of every kernel class from two rocprofv3 --pmc runs
+    (FETCH_SIZE, then WRITE_SIZE, both in KiB), scaled by the counter readings of the
+    calibration copy (reads and writes COPY_BYTES)."""
+    import csv
+    per = {}
+    for path, counter in ((fetch_csv, "FETCH_SIZE"), (write_csv, "WRITE_SIZE")):
+        rows = {}
+        with open(path) as f:
+            for row in csv.DictReader(f):
+                if row["Counter_Name"] != counter:
+                    continue
+                key = row["Dispatch_Id"]
+                rows.setdefault(key, [row["Kernel_Name"], 0.0])[1] += float(row["Counter_Value"]) * 1024.0
+        copy = [v for n, v in rows.values() if "neg_kernel" in n]
+        if not copy:
+            raise SystemExit(f"no calibration copy dispatch in {path}")
+        factor = COPY_BYTES / max(copy)
+        per[counter] = factor
+        for n, v in rows.values():
+            kc = _kernel_class(n)
+            if kc is None:
+                continue
+            d = per.setdefault(f"{kc[0]}/{kc[1]}", {})
+            d.setdefault(counter, []).append(v)
+    out = {"source_sha256": source_digest(), "copy_bytes": COPY_BYTES,
+           "factor_fetch": per.pop("FETCH_SIZE"), "factor_write": per.pop("WRITE_SIZE"), "kernels": {}}
+    for k, d in sorted(per.items()):
+        if "FETCH_SIZE" in d and "WRITE_SIZE" in d:
+            fb = float(np.mean(d["FETCH_SIZE"])) * out["factor_fetch"]
+            wb = float(np.mean(d["WRITE_SIZE"])) * out["factor_write"]
+            out["kernels"][k] = {"dispatches": len(d["FETCH_SIZE"]), "fetch_bytes": round(fb),
+                                 "write_bytes": round(wb), "bytes_per_launch": round(fb + wb)}
+    return out
+
+
+def load_traffic(workload):
+    """Calibrated HBM bytes per launch from the committed counter summary, if it
+    was taken on the current sources."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    a = text.find("```json")
+    if a < 0:
+        return None
+    b = text.find("```", a + 7)
+    data = json.loads(text[a + 7:b])
+    if data.get("source_sha256") != source_digest():
+        log("counter summary was taken on other sources: traffic null")
+        return None
+    return data
 
 
 def cpu_baseline(cfg, fp64_iters, sample_cut=2000, sample_iters=2):
@@ -101,7 +193,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--workload", default="spheres128", choices=["spheres128", "ellipsoids256"])
+    ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="summarise two rocprofv3 --pmc runs of this script (FETCH_SIZE, WRITE_SIZE) as JSON")
     args = ap.parse_args()
+    if args.pmc_summary:
+        print(json.dumps(pmc_summary(*args.pmc_summary), indent=1))
+        return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
               "(load cases and RVEs would be sharded across GPUs, see DESIGN.md)", file=sys.stderr)
@@ -134,6 +231,12 @@ def main():
     lay = pm.layout(with_arrays=False)
     lay.update(n0=cfg["n"][0], n1=cfg["n"][1], n2=cfg["n"][2])
     log(f"setup {setup_s:.3f}s, nX={lay['nX']}, irregular voxels={lay['n_irregular_voxels']}")
+
+    # calibration copy for the byte counters (outside the timed region)
+    src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
+    dst = torch.neg(src)
+    torch.cuda.synchronize()
+    del src, dst
 
     for _ in range(args.warmup):
         pm.solve(E, c_eff=True)
@@ -198,10 +301,15 @@ def main():
         active = 6.0
     bytes_launch = byts[dom_prec][dom] * active / 6.0
     achieved = bytes_launch / (dom_ms * 1e-3) / 1e9 if dom_ms > 0 else 0.0
+    traffic = None
+    tr = load_traffic(args.workload)
+    if tr is not None and f"{dom}/{dom_prec}" in tr["kernels"]:
+        traffic = tr["kernels"][f"{dom}/{dom_prec}"]["bytes_per_launch"]
     roofline = dict(bound="hbm", kernel=f"{dom} ({dom_prec})", achieved=round(achieved, 1), peak=HBM_PEAK_GBS,
-                    unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
+                    unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
                     bytes_per_launch=int(bytes_launch), ms_per_launch=round(dom_ms, 5), launches=dom_n,
-                    mean_active_loads=round(active, 3))
+                    mean_active_loads=round(active, 3),
+                    traffic_over_algorithmic=round(traffic / bytes_launch, 3) if traffic else None)
     # per-kernel breakdown of one CG iteration with all six loads active
     prof = pm.profile(precision="fp32", nrhs=6, nrep=10)
     kernels = {k: dict(ms=round(v[0], 5), launches_per_iter=v[1] / 10.0,

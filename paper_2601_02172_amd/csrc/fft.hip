@@ -367,7 +367,7 @@ __global__ __launch_bounds__(256) void k_fft_x_inv(FftArgs A, FftPlan pl, const 
 template <int N> struct PlaneCfg {
     static constexpr int NH = N / 2 + 1;
     static constexpr int NP = N / 2;
-    static constexpr int LS = N + 1;
+    static constexpr int LS = fft_ls(N);
     static constexpr int NT = 1024;
     static constexpr int ELEMS = NH * LS;      // >= NP * LS
 };
@@ -400,7 +400,7 @@ __global__ __launch_bounds__(1024) void k_fft_plane_fwd(FftArgs A, const cpx<T> 
             fr[o0] = a;
             fr[o1] = b;
         }
-        sh[pp * C::LS + x] = {a, b};
+        sh[pp * C::LS + fft_pad(x)] = {a, b};
     }
     __syncthreads();
     fft_lines<T, N, C::NP, C::NT, false>(sh, tw);
@@ -413,8 +413,8 @@ __global__ __launch_bounds__(1024) void k_fft_plane_fwd(FftArgs A, const cpx<T> 
         const int idx = threadIdx.x + i * C::NT;
         if (idx < NOUT) {
             const int pp = idx / C::NH, kx = idx - pp * C::NH;
-            const cpx<T> Zk = sh[pp * C::LS + kx];
-            const cpx<T> Zm = sh[pp * C::LS + (kx == 0 ? 0 : N - kx)];
+            const cpx<T> Zk = sh[pp * C::LS + fft_pad(kx)];
+            const cpx<T> Zm = sh[pp * C::LS + fft_pad(kx == 0 ? 0 : N - kx)];
             ra[i] = {(T)0.5 * (Zk.x + Zm.x), (T)0.5 * (Zk.y - Zm.y)};
             rb[i] = {(T)0.5 * (Zk.y + Zm.y), (T)-0.5 * (Zk.x - Zm.x)};
         }
@@ -425,8 +425,8 @@ __global__ __launch_bounds__(1024) void k_fft_plane_fwd(FftArgs A, const cpx<T> 
         const int idx = threadIdx.x + i * C::NT;
         if (idx < NOUT) {
             const int pp = idx / C::NH, kx = idx - pp * C::NH;
-            sh[kx * C::LS + 2 * pp] = ra[i];
-            sh[kx * C::LS + 2 * pp + 1] = rb[i];
+            sh[kx * C::LS + fft_pad(2 * pp)] = ra[i];
+            sh[kx * C::LS + fft_pad(2 * pp + 1)] = rb[i];
         }
     }
     __syncthreads();
@@ -434,7 +434,7 @@ __global__ __launch_bounds__(1024) void k_fft_plane_fwd(FftArgs A, const cpx<T> 
     cpx<T> *sr = spec + (int64_t)r * 3 * A.specN + (int64_t)c * A.specN;
     for (int idx = threadIdx.x; idx < N * C::NH; idx += C::NT) {
         const int ky = idx / C::NH, kx = idx - ky * C::NH;
-        sr[((int64_t)ky * A.n2 + kz) * C::NH + kx] = sh[kx * C::LS + ky];
+        sr[((int64_t)ky * A.n2 + kz) * C::NH + kx] = sh[kx * C::LS + fft_pad(ky)];
     }
 }
 
@@ -451,7 +451,7 @@ __global__ __launch_bounds__(1024) void k_fft_plane_inv(FftArgs A, const cpx<T> 
     const cpx<T> *sr = spec + (int64_t)r * 3 * A.specN + (int64_t)c * A.specN;
     for (int idx = threadIdx.x; idx < N * C::NH; idx += C::NT) {
         const int ky = idx / C::NH, kx = idx - ky * C::NH;
-        sh[kx * C::LS + ky] = sr[((int64_t)ky * A.n2 + kz) * C::NH + kx];
+        sh[kx * C::LS + fft_pad(ky)] = sr[((int64_t)ky * A.n2 + kz) * C::NH + kx];
     }
     __syncthreads();
     fft_lines<T, N, C::NH, C::NT, true>(sh, tw);
@@ -466,7 +466,7 @@ __global__ __launch_bounds__(1024) void k_fft_plane_inv(FftArgs A, const cpx<T> 
             const int pp = idx / N, k = idx - pp * N;
             const bool lo = k < C::NH;
             const int kk = lo ? k : N - k;
-            cpx<T> Av = sh[kk * C::LS + 2 * pp], Bv = sh[kk * C::LS + 2 * pp + 1];
+            cpx<T> Av = sh[kk * C::LS + fft_pad(2 * pp)], Bv = sh[kk * C::LS + fft_pad(2 * pp + 1)];
             if (!lo) { Av.y = -Av.y; Bv.y = -Bv.y; }
             rz[i] = {Av.x - Bv.y, Av.y + Bv.x};
         }
@@ -477,7 +477,7 @@ __global__ __launch_bounds__(1024) void k_fft_plane_inv(FftArgs A, const cpx<T> 
         const int idx = threadIdx.x + i * C::NT;
         if (idx < NOUT) {
             const int pp = idx / N, k = idx - pp * N;
-            sh[pp * C::LS + k] = rz[i];
+            sh[pp * C::LS + fft_pad(k)] = rz[i];
         }
     }
     __syncthreads();
@@ -487,7 +487,7 @@ __global__ __launch_bounds__(1024) void k_fft_plane_inv(FftArgs A, const cpx<T> 
     if (mode == 1) { alpha = (T)A.scal[r].alpha; beta = (T)A.scal[r].beta; }
     for (int idx = threadIdx.x; idx < C::NP * N; idx += C::NT) {
         const int pp = idx / N, x = idx - pp * N;
-        const cpx<T> yv = sh[pp * C::LS + x];
+        const cpx<T> yv = sh[pp * C::LS + fft_pad(x)];
         const int64_t o0 = base + (2 * pp) * N + x, o1 = o0 + N;
         if (mode == 0) {
             out[o0] = yv.x;
@@ -507,10 +507,13 @@ __global__ __launch_bounds__(1024) void k_fft_plane_inv(FftArgs A, const cpx<T> 
 
 // ---------------------------------------------------------------- z pass, compile-time length
 // Element (c, kz, ky, kx) of the spectrum at c * specN + kz * sz + ky * sy + kx.
+// One workgroup per (ky, run of tk kx columns, load); the ceil(nh / TK) runs
+// share the nh columns evenly (tk <= TK), so no run is mostly padding.  LDS
+// line c * tk + kl holds component c of column kx0 + kl.
 template <typename T, int N2, int TK>
 __global__ __launch_bounds__(512) void k_fft_z_t(FftArgs A, const cpx<T> *tw, const T *h0, const T *h1,
                                                   const T *h2, cpx<T> *spec, int64_t sz, int64_t sy) {
-    constexpr int LS = N2 + 1;
+    constexpr int LS = fft_ls(N2);
     constexpr int NL = 3 * TK;
     extern __shared__ unsigned char smem_raw[];
     cpx<T> *sh = reinterpret_cast<cpx<T> *>(smem_raw);
@@ -519,26 +522,29 @@ __global__ __launch_bounds__(512) void k_fft_z_t(FftArgs A, const cpx<T> *tw, co
     if (!active_rhs(A, r)) return;
     const int nh = A.nh;
     const int ntiles = (nh + TK - 1) / TK;
+    const int tk = (nh + ntiles - 1) / ntiles;
     const int tile = blockIdx.x % ntiles;
     const int ky = blockIdx.x / ntiles;
-    const int kx0 = tile * TK;
+    const int kx0 = tile * tk;
+    const int ncol = min(tk, nh - kx0);
     cpx<T> *base = spec + (int64_t)r * 3 * A.specN + (int64_t)ky * sy + kx0;
     for (int idx = threadIdx.x; idx < NL * N2; idx += 512) {
         const int kl = idx % TK, rest = idx / TK;
         const int zz = rest % N2, c = rest / N2;
-        sh[(c * TK + kl) * LS + zz] = (kx0 + kl < nh) ? base[(int64_t)c * A.specN + zz * sz + kl] : cpx<T>{0, 0};
+        if (kl < tk)
+            sh[(c * tk + kl) * LS + fft_pad(zz)] = kl < ncol ? base[(int64_t)c * A.specN + zz * sz + kl] : cpx<T>{0, 0};
     }
     __syncthreads();
-    fft_lines<T, N2, NL, 512, false>(sh, tw);
+    fft_lines<T, N2, NL, 512, false>(sh, tw, 3 * tk);
     double part = 0.0;
     const T scale = (T)(1.0 / ((double)A.n0 * (double)A.n1 * (double)N2));
     for (int idx = threadIdx.x; idx < TK * N2; idx += 512) {
         const int kl = idx % TK, zz = idx / TK;
         const int kx = kx0 + kl;
-        if (kx < nh) {
+        if (kl < ncol) {
             cpx<T> fv[3];
 #pragma unroll
-            for (int c = 0; c < 3; ++c) fv[c] = sh[(c * TK + kl) * LS + zz];
+            for (int c = 0; c < 3; ++c) fv[c] = sh[(c * tk + kl) * LS + fft_pad(zz)];
             const cpx<T> f0[3] = {fv[0], fv[1], fv[2]};
             green_apply<T>(h0[2 * kx], h0[2 * kx + 1], h1[2 * ky], h1[2 * ky + 1], h2[2 * zz], h2[2 * zz + 1], fv,
                            kx == 0 && ky == 0 && zz == 0);
@@ -548,17 +554,17 @@ __global__ __launch_bounds__(512) void k_fft_z_t(FftArgs A, const cpx<T> *tw, co
                 fv[c].x *= scale;
                 fv[c].y *= scale;
                 q += (double)f0[c].x * (double)fv[c].x + (double)f0[c].y * (double)fv[c].y;
-                sh[(c * TK + kl) * LS + zz] = fv[c];
+                sh[(c * tk + kl) * LS + fft_pad(zz)] = fv[c];
             }
             part += ((kx == 0 || 2 * kx == A.n0) ? 1.0 : 2.0) * q;
         }
     }
     __syncthreads();
-    fft_lines<T, N2, NL, 512, true>(sh, tw);
+    fft_lines<T, N2, NL, 512, true>(sh, tw, 3 * tk);
     for (int idx = threadIdx.x; idx < NL * N2; idx += 512) {
         const int kl = idx % TK, rest = idx / TK;
         const int zz = rest % N2, c = rest / N2;
-        if (kx0 + kl < nh) base[(int64_t)c * A.specN + zz * sz + kl] = sh[(c * TK + kl) * LS + zz];
+        if (kl < ncol) base[(int64_t)c * A.specN + zz * sz + kl] = sh[(c * tk + kl) * LS + fft_pad(zz)];
     }
     double v[1] = {part};
     block_sum<1>(v, red);
@@ -608,7 +614,7 @@ static bool ztmpl_size(int n) { return plane_size(n) || n == 256; }
 
 template <typename T> static bool plane_path(const Geometry &g) {
     return g.n0 == g.n1 && plane_size(g.n0) &&
-           (size_t)(g.n0 / 2 + 1) * (g.n0 + 1) * sizeof(cpx<T>) <= (size_t)160 * 1024;
+           (size_t)(g.n0 / 2 + 1) * fft_ls(g.n0) * sizeof(cpx<T>) <= (size_t)160 * 1024;
 }
 template <typename T> static constexpr int tkz_t() { return sizeof(T) == 8 ? 8 : 16; }
 
@@ -646,7 +652,7 @@ static void plane_inv(FftArgs A, dim3 grid, hipStream_t s, const cpx<T> *tw, con
 template <typename T, int N2>
 static void zpass(FftArgs A, dim3 grid, hipStream_t s, const Tables<T> &tb, cpx<T> *spec, int64_t sz, int64_t sy) {
     constexpr int TK = tkz_t<T>();
-    const size_t lds = (size_t)3 * TK * (N2 + 1) * sizeof(cpx<T>);
+    const size_t lds = (size_t)3 * TK * fft_ls(N2) * sizeof(cpx<T>);
     static bool init = false;
     if (!init) { allow_lds(k_fft_z_t<T, N2, TK>, lds); init = true; }
     k_fft_z_t<T, N2, TK><<<grid, 512, lds, s>>>(A, tb.tw[2], tb.half[0], tb.half[1], tb.half[2], spec, sz, sy);

@@ -164,7 +164,7 @@ __device__ __forceinline__ void regular_voxel(const T (&U)[8][3], const T (&eb)[
 template <typename T, bool HX, bool EB, bool ST>
 __global__ __launch_bounds__(256) void k_regular(OpArgs<T> A) {
     __shared__ T Dp[3][TC * TC][3];
-    __shared__ T FB[TE * TE][18];
+    __shared__ T FB[18][TE * TE];      // structure of arrays: lanes hit consecutive banks
     __shared__ double red[4 * 7];
 
     const int r = blockIdx.z;
@@ -274,12 +274,12 @@ __global__ __launch_bounds__(256) void k_regular(OpArgs<T> A) {
         // publish the corners that belong to other threads' nodes
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
-            FB[tid][0 + i] = F[1][i];
-            FB[tid][3 + i] = F[2][i];
-            FB[tid][6 + i] = F[3][i];
-            FB[tid][9 + i] = F[5][i];
-            FB[tid][12 + i] = F[6][i];
-            FB[tid][15 + i] = F[7][i];
+            FB[0 + i][tid] = F[1][i];
+            FB[3 + i][tid] = F[2][i];
+            FB[6 + i][tid] = F[3][i];
+            FB[9 + i][tid] = F[5][i];
+            FB[12 + i][tid] = F[6][i];
+            FB[15 + i][tid] = F[7][i];
         }
         if (more) store_plane((s + 2) % 3);
         __syncthreads();
@@ -287,8 +287,8 @@ __global__ __launch_bounds__(256) void k_regular(OpArgs<T> A) {
             T bot[3], top[3];
 #pragma unroll
             for (int i = 0; i < 3; ++i) {
-                bot[i] = F[0][i] + FB[tid - 1][0 + i] + FB[tid - 16][3 + i] + FB[tid - 17][6 + i];
-                top[i] = F[4][i] + FB[tid - 1][9 + i] + FB[tid - 16][12 + i] + FB[tid - 17][15 + i];
+                bot[i] = F[0][i] + FB[0 + i][tid - 1] + FB[3 + i][tid - 16] + FB[6 + i][tid - 17];
+                top[i] = F[4][i] + FB[9 + i][tid - 1] + FB[12 + i][tid - 16] + FB[15 + i][tid - 17];
             }
             if (kl >= k0) {
                 double dot = 0.0;
