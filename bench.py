@@ -30,6 +30,15 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# VALU issue rate without packed FP32: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz,
+# one add, multiply or fused multiply-add per lane and cycle (FP32 and FP64 alike)
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+# arithmetic operations per voxel of the regular-voxel operator (six Kuhn tets by
+# their 12 shared edges): 36 edge differences, 6 x 18 per tet (3 shear sums,
+# trace, 3 normal and 3 shear stresses, 6 edge-force accumulations), 48 for the
+# corner forces from the edge forces, 24 for the node sums and the sign, 3 for
+# lambda V, mu V and 2 mu V
+REGULAR_OPS_PER_VOXEL = 36 + 6 * 18 + 48 + 24 + 3
 # copy-like calibration kernel for the HBM byte counters: elementwise negation of
 # a float32 buffer reads and writes exactly COPY_BYTES each
 COPY_BYTES = 256 << 20
@@ -305,18 +314,30 @@ def main():
     tr = load_traffic(args.workload)
     if tr is not None and f"{dom}/{dom_prec}" in tr["kernels"]:
         traffic = tr["kernels"][f"{dom}/{dom_prec}"]["bytes_per_launch"]
-    roofline = dict(bound="hbm", kernel=f"{dom} ({dom_prec})", achieved=round(achieved, 1), peak=HBM_PEAK_GBS,
-                    unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
-                    bytes_per_launch=int(bytes_launch), ms_per_launch=round(dom_ms, 5), launches=dom_n,
-                    mean_active_loads=round(active, 3),
-                    traffic_over_algorithmic=round(traffic / bytes_launch, 3) if traffic else None)
+    # the binding roof: the larger of the ideal memory time and the ideal VALU time
+    ops_launch = REGULAR_OPS_PER_VOXEL * lay["N"] * active if dom == "regular_voxels" else None
+    t_hbm = bytes_launch / (HBM_PEAK_GBS * 1e9)
+    t_alu = ops_launch / (VALU_PEAK_TOPS * 1e12) if ops_launch else 0.0
+    common = dict(kernel=f"{dom} ({dom_prec})", traffic=traffic, bytes_per_launch=int(bytes_launch),
+                  ms_per_launch=round(dom_ms, 5), launches=dom_n, mean_active_loads=round(active, 3),
+                  traffic_over_algorithmic=round(traffic / bytes_launch, 3) if traffic else None,
+                  hbm_gbs=round(achieved, 1), hbm_frac=round(achieved / HBM_PEAK_GBS, 4))
+    if t_alu > t_hbm:
+        tops = ops_launch / (dom_ms * 1e-3) / 1e12
+        roofline = dict(bound="alu", achieved=round(tops, 3), peak=round(VALU_PEAK_TOPS, 2),
+                        unit="Tops/s (VALU lane operations, no packed FP32)", frac=round(tops / VALU_PEAK_TOPS, 4),
+                        ops_per_launch=int(ops_launch), **common)
+    else:
+        roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                        frac=round(achieved / HBM_PEAK_GBS, 4), **common)
     # per-kernel breakdown of one CG iteration with all six loads active
     prof = pm.profile(precision="fp32", nrhs=6, nrep=10)
     kernels = {k: dict(ms=round(v[0], 5), launches_per_iter=v[1] / 10.0,
                        gbs=round(byts["fp32"][k] / (v[0] * 1e-3) / 1e9, 1) if v[0] > 0 and byts["fp32"][k] else None)
                for k, v in prof.items()}
     region_summary = {f"{k[0]}/{k[1]}": [round(v[0], 5), v[1]] for k, v in region.items() if v[1]}
-    log(f"dominant kernel {dom}: {dom_ms:.4f} ms, {achieved:.0f} GB/s")
+    log(f"dominant kernel {dom}: {dom_ms:.4f} ms, {achieved:.0f} GB/s, roofline {roofline['bound']} "
+        f"frac {roofline['frac']}")
     grad_info = None
     if args.workload == "ellipsoids256":
         # loss ||C_eff - C_t||_F^2 with C_t = C_eff at the median moduli; gradient over all Lame pairs

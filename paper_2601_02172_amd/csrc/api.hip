@@ -616,7 +616,7 @@ void xfft_destroy(xfft_problem *p) {
     if (p->stream) (void)hipStreamSynchronize(p->stream);
     void *ptrs[] = {p->Ls, p->phase, p->vmat, p->irr, p->irr_j, p->irr_lab, p->jlist, p->enr_src, p->d0, p->partial,
                     p->scal, p->flags, p->ebar, p->sol_u, p->sol_ue, p->t64.lame, p->t64.d0is, p->t64.irr_L,
-                    p->t32.lame, p->t32.d0is, p->t32.irr_L};
+                    p->t32.lame, p->t32.d0is, p->t32.irr_L, p->t64.irr_M, p->t32.irr_M};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     for (int a = 0; a < 3; ++a) {

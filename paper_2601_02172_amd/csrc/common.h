@@ -99,6 +99,11 @@ template <typename T> struct Tables {
     T *lame = nullptr;       // [nphase][2]
     T *d0is = nullptr;       // [nX] D0^-1/2
     T *irr_L = nullptr;      // [nirr][8] snapped corner level set of irregular voxels
+    // [120][nirr] side moments of the Kuhn tets of irregular voxels, computed in
+    // FP64 and rounded once: row 20 t + k, k < 10 the + side and k >= 10 the -
+    // side, each the upper triangle of the symmetric 4 x 4 matrix row by row
+    // (rows of uncut tets hold zeros)
+    T *irr_M = nullptr;
     cpx<T> *tw[3] = {nullptr, nullptr, nullptr};   // twiddles exp(-2 pi i t / n_axis)
     T *half[3] = {nullptr, nullptr, nullptr};      // [n_axis][2]: sin, cos of pi k / n_axis
 };

@@ -34,7 +34,8 @@ struct OpArgs {
     int parity;
     const int32_t *vmat, *irr, *irr_j, *irr_lab, *jlist, *enr_src;
     const T *d0is, *lame;
-    const double *irr_L64;    // [nirr][8] corner level set (FP64 for every precision)
+    const T *irr_L;           // [nirr][8] corner level set
+    const T *irr_M;           // [120][nirr] precomputed side moments
     T *cutbuf;
     double *partial;
     int nslots, slot0;
@@ -317,16 +318,15 @@ __global__ __launch_bounds__(256) void k_regular(OpArgs<T> A) {
 
 // ---------------------------------------------------------------- irregular voxel
 template <int t, typename T, bool EB>
-__device__ __forceinline__ void irregular_tet(const double (&Lc)[8], const T (&U)[8][3], const T (&Q)[8][3],
+__device__ __forceinline__ void irregular_tet(const T (&Lc)[8], const T *__restrict__ Mq, int64_t nirr,
+                                              const T (&U)[8][3], const T (&Q)[8][3],
                                               const int32_t *lab, const T *lame, const Sym<T> &eb,
                                               T (&F)[8][3], T (&Fe)[8][3], Sym<T> &S) {
     constexpr int p0 = perm_axis(t, 0), p1 = perm_axis(t, 1), p2 = perm_axis(t, 2);
     T L[4], u[4][3], q[4][3];
-    double Ld[4];
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
-        Ld[a] = Lc[tet_corner(t, a)];
-        L[a] = (T)Ld[a];
+        L[a] = Lc[tet_corner(t, a)];
 #pragma unroll
         for (int i = 0; i < 3; ++i) { u[a][i] = U[tet_corner(t, a)][i]; q[a][i] = Q[tet_corner(t, a)][i]; }
     }
@@ -345,15 +345,20 @@ __device__ __forceinline__ void irregular_tet(const double (&Lc)[8], const T (&U
         sym_axpy(S, (T)1, s);
         return;
     }
-    // Side moments always in FP64: the smaller side of a nearly degenerate
-    // split is a difference of O(1) moments and loses all digits in FP32.
-    double Mpd[4][4], Mmd[4][4];
-    side_moments<double>(Ld, 1.0 / 6.0, Mpd, Mmd);
+    // Side moments, precomputed in FP64 at setup (the smaller side of a nearly
+    // degenerate split is a difference of O(1) moments and would lose all
+    // digits in FP32) and rounded once to T.
     T Mp[4][4], Mm[4][4];
+    {
+        int k = 0;
 #pragma unroll
-    for (int c = 0; c < 4; ++c)
+        for (int c = 0; c < 4; ++c)
 #pragma unroll
-        for (int d = 0; d < 4; ++d) { Mp[c][d] = (T)Mpd[c][d]; Mm[c][d] = (T)Mmd[c][d]; }
+            for (int d = c; d < 4; ++d, ++k) {
+                Mp[c][d] = Mp[d][c] = Mq[(int64_t)(20 * t + k) * nirr];
+                Mm[c][d] = Mm[d][c] = Mq[(int64_t)(20 * t + 10 + k) * nirr];
+            }
+    }
     const Grad<T> Hq = kuhn_grad<t>(q);
 #pragma unroll
     for (int side = 0; side < 2; ++side) {
@@ -418,7 +423,7 @@ __global__ __launch_bounds__(128) void k_irregular(OpArgs<T> A) {
         const int64_t N = A.N;
         const int64_t vox = A.irr[qv];
         const int i = (int)(vox % A.n0), j = (int)((vox / A.n0) % A.n1), k = (int)(vox / ((int64_t)A.n0 * A.n1));
-        double Lc[8];
+        T Lc[8];
         T U[8][3], Q[8][3], sc[8];
         const T *x = HX ? A.x + (int64_t)r * 3 * N : nullptr;
         const T *xe = HX ? A.xe + (int64_t)r * 3 * A.nX : nullptr;
@@ -426,7 +431,7 @@ __global__ __launch_bounds__(128) void k_irregular(OpArgs<T> A) {
         for (int c = 0; c < 8; ++c) {
             const int64_t node = wrapi(i + (c & 1), A.n0) +
                                  (int64_t)A.n0 * (wrapi(j + ((c >> 1) & 1), A.n1) + (int64_t)A.n1 * wrapi(k + (c >> 2), A.n2));
-            Lc[c] = A.irr_L64[qv * 8 + c];
+            Lc[c] = A.irr_L[qv * 8 + c];
             const int jc = A.irr_j[qv * 8 + c];
             sc[c] = jc >= 0 ? A.d0is[jc] : (T)0;
 #pragma unroll
@@ -444,12 +449,12 @@ __global__ __launch_bounds__(128) void k_irregular(OpArgs<T> A) {
 #pragma unroll
             for (int d = 0; d < 3; ++d) F[c][d] = Fe[c][d] = (T)0;
         Sym<T> S = sym_zero<T>();
-        irregular_tet<0, T, EB>(Lc, U, Q, lab, A.lame, eb, F, Fe, S);
-        irregular_tet<1, T, EB>(Lc, U, Q, lab, A.lame, eb, F, Fe, S);
-        irregular_tet<2, T, EB>(Lc, U, Q, lab, A.lame, eb, F, Fe, S);
-        irregular_tet<3, T, EB>(Lc, U, Q, lab, A.lame, eb, F, Fe, S);
-        irregular_tet<4, T, EB>(Lc, U, Q, lab, A.lame, eb, F, Fe, S);
-        irregular_tet<5, T, EB>(Lc, U, Q, lab, A.lame, eb, F, Fe, S);
+        irregular_tet<0, T, EB>(Lc, A.irr_M + qv, A.nirr, U, Q, lab, A.lame, eb, F, Fe, S);
+        irregular_tet<1, T, EB>(Lc, A.irr_M + qv, A.nirr, U, Q, lab, A.lame, eb, F, Fe, S);
+        irregular_tet<2, T, EB>(Lc, A.irr_M + qv, A.nirr, U, Q, lab, A.lame, eb, F, Fe, S);
+        irregular_tet<3, T, EB>(Lc, A.irr_M + qv, A.nirr, U, Q, lab, A.lame, eb, F, Fe, S);
+        irregular_tet<4, T, EB>(Lc, A.irr_M + qv, A.nirr, U, Q, lab, A.lame, eb, F, Fe, S);
+        irregular_tet<5, T, EB>(Lc, A.irr_M + qv, A.nirr, U, Q, lab, A.lame, eb, F, Fe, S);
         T *cb = A.cutbuf + ((int64_t)r * A.nirr + qv) * 48;
 #pragma unroll
         for (int c = 0; c < 8; ++c) {
@@ -526,7 +531,7 @@ void launch_operator(xfft_problem *p, Work<T> &w, const Tables<T> &tb, const T *
     A.ebar = p->ebar; A.sign = sign; A.flags = flags; A.parity = parity;
     A.vmat = p->vmat; A.irr = p->irr; A.irr_j = p->irr_j; A.irr_lab = p->irr_lab; A.jlist = p->jlist;
     A.enr_src = p->enr_src;
-    A.irr_L64 = p->t64.irr_L; A.d0is = tb.d0is; A.lame = tb.lame;
+    A.irr_L = tb.irr_L; A.irr_M = tb.irr_M; A.d0is = tb.d0is; A.lame = tb.lame;
     A.cutbuf = w.cutbuf; A.partial = p->partial; A.nslots = p->nslots;
     A.vstress = vstress;
     A.n0 = g.n0; A.n1 = g.n1; A.n2 = g.n2; A.N = g.N; A.nX = g.nX; A.nirr = g.nirr;

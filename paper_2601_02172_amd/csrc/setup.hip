@@ -205,6 +205,47 @@ __global__ void k_irr_tables(int64_t nirr, int n0, int n1, int n2, const int32_t
     irr_labels_tet<5>(Lc, pc, lab);
 }
 
+// Side moments of the six Kuhn tets of every irregular voxel (eq. of the exact
+// integration over the two sides of a cut element): geometry only, so they are
+// computed once per setup instead of in every operator application.
+__global__ void k_irr_moments(int64_t nirr, const double *irr_L64, double *M64, float *M32) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nirr) return;
+    double Lc[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) Lc[c] = irr_L64[q * 8 + c];
+    for (int t = 0; t < 6; ++t) {
+        double L[4];
+        bool anyp = false, anyn = false;
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+            L[a] = Lc[tet_corner(t, a)];
+            anyp |= L[a] > 0.0;
+            anyn |= L[a] < 0.0;
+        }
+        double Mp[4][4], Mm[4][4];
+        if (anyp && anyn) {
+            side_moments<double>(L, 1.0 / 6.0, Mp, Mm);
+        } else {
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+#pragma unroll
+                for (int d = 0; d < 4; ++d) Mp[c][d] = Mm[c][d] = 0.0;
+        }
+        int k = 0;
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+#pragma unroll
+            for (int d = c; d < 4; ++d, ++k) {
+                const int64_t op = (int64_t)(20 * t + k) * nirr + q, om = (int64_t)(20 * t + 10 + k) * nirr + q;
+                M64[op] = Mp[c][d];
+                M64[om] = Mm[c][d];
+                M32[op] = (float)Mp[c][d];
+                M32[om] = (float)Mm[c][d];
+            }
+    }
+}
+
 // int over both sides of |grad N_X^a|^2 for vertex a of cut Kuhn tet t
 template <int t>
 __device__ __forceinline__ double d0_tet(const double (&Lc)[8], int corner) {
@@ -409,6 +450,8 @@ int run_setup(xfft_problem *p, const double *L_dev_raw) {
             hipMalloc(&p->irr_lab, sizeof(int32_t) * 12 * nirr) != hipSuccess ||
             hipMalloc(&p->t64.irr_L, sizeof(double) * 8 * nirr) != hipSuccess ||
             hipMalloc(&p->t32.irr_L, sizeof(float) * 8 * nirr) != hipSuccess ||
+            hipMalloc(&p->t64.irr_M, sizeof(double) * 120 * nirr) != hipSuccess ||
+            hipMalloc(&p->t32.irr_M, sizeof(float) * 120 * nirr) != hipSuccess ||
             hipMalloc(&p->d0, sizeof(double) * nX) != hipSuccess ||
             hipMalloc(&p->t64.d0is, sizeof(double) * nX) != hipSuccess ||
             hipMalloc(&p->t32.d0is, sizeof(float) * nX) != hipSuccess ||
@@ -419,6 +462,8 @@ int run_setup(xfft_problem *p, const double *L_dev_raw) {
         k_irr_tables<<<(unsigned)((g.nirr + tb - 1) / tb), tb, 0, s>>>(g.nirr, g.n0, g.n1, g.n2, p->irr, p->Ls,
                                                                        p->phase, jmap, p->irr_j, p->irr_lab,
                                                                        p->t64.irr_L, p->t32.irr_L);
+        k_irr_moments<<<(unsigned)((g.nirr + tb - 1) / tb), tb, 0, s>>>(g.nirr, p->t64.irr_L, p->t64.irr_M,
+                                                                        p->t32.irr_M);
     }
     if (!rc && g.nX > 0) {
         k_d0<<<(unsigned)((g.nX + tb - 1) / tb), tb, 0, s>>>(g.nX, g.n0, g.n1, g.n2, p->jlist, p->vmat, p->t64.irr_L,
