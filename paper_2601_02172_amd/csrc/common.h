@@ -46,6 +46,17 @@ template <typename T> __device__ __forceinline__ cpx<T> cmul(cpx<T> a, cpx<T> b)
 template <typename T> __device__ __forceinline__ cpx<T> cadd(cpx<T> a, cpx<T> b) { return {a.x + b.x, a.y + b.y}; }
 template <typename T> __device__ __forceinline__ cpx<T> csub(cpx<T> a, cpx<T> b) { return {a.x - b.x, a.y - b.y}; }
 
+// Workgroups of a dispatch are handed to the 8 XCDs of the chip round robin
+// (linear id mod 8), and each XCD has its own L2.  Giving every XCD one
+// contiguous range of logical ids keeps neighbouring tiles, which read the same
+// cache lines, on the same L2.  Bijective on [0, nb).
+__device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t nb) {
+    constexpr int NXCD = 8;
+    const int64_t q = nb / NXCD, rem = nb % NXCD;
+    const int64_t x = b % NXCD, slot = b / NXCD;
+    return x < rem ? x * (q + 1) + slot : rem * (q + 1) + (x - rem) * q + slot;
+}
+
 // ------------------------------------------------------------------ FFT plan
 struct FftPlan {
     int n;            // line length

@@ -246,13 +246,15 @@ __global__ __launch_bounds__(512) void k_fft_z_green(FftArgs A, FftPlan pl, cons
     extern __shared__ unsigned char smem_raw[];
     cpx<T> *sh = reinterpret_cast<cpx<T> *>(smem_raw);
     __shared__ double red[8];
-    const int r = blockIdx.y;
-    if (!active_rhs(A, r)) return;
     const int n1 = A.n1, n2 = A.n2, nh = A.nh;
     const int lstride = n2 + 1;
     const int ntiles = (nh + tk - 1) / tk;
-    const int tile = blockIdx.x % ntiles;
-    const int ky = blockIdx.x / ntiles;
+    const int nblk = n1 * ntiles;                   // workgroups per right-hand side
+    const int64_t lb = xcd_remap(blockIdx.x, gridDim.x);
+    const int r = (int)(lb / nblk), blk = (int)(lb % nblk);
+    if (!active_rhs(A, r)) return;
+    const int tile = blk % ntiles;
+    const int ky = blk / ntiles;
     const int kx0 = tile * tk;
     cpx<T> *base = spec + (int64_t)r * 3 * A.specN;
     for (int idx = threadIdx.x; idx < 3 * tk * n2; idx += blockDim.x) {
@@ -299,7 +301,7 @@ __global__ __launch_bounds__(512) void k_fft_z_green(FftArgs A, FftPlan pl, cons
     double v[1] = {part};
     block_sum<1>(v, red);
     if (threadIdx.x == 0) {
-        double *P = A.partial + ((int64_t)r * A.nslots + A.slot0 + blockIdx.x) * NPART;
+        double *P = A.partial + ((int64_t)r * A.nslots + A.slot0 + blk) * NPART;
         P[0] = v[0];
 #pragma unroll
         for (int q = 1; q < 7; ++q) P[q] = 0.0;
@@ -518,13 +520,15 @@ __global__ __launch_bounds__(512) void k_fft_z_t(FftArgs A, const cpx<T> *tw, co
     extern __shared__ unsigned char smem_raw[];
     cpx<T> *sh = reinterpret_cast<cpx<T> *>(smem_raw);
     __shared__ double red[8];
-    const int r = blockIdx.y;
-    if (!active_rhs(A, r)) return;
     const int nh = A.nh;
     const int ntiles = (nh + TK - 1) / TK;
+    const int nblk = A.n1 * ntiles;                 // workgroups per right-hand side
+    const int64_t lb = xcd_remap(blockIdx.x, gridDim.x);
+    const int r = (int)(lb / nblk), blk = (int)(lb % nblk);
+    if (!active_rhs(A, r)) return;
     const int tk = (nh + ntiles - 1) / ntiles;
-    const int tile = blockIdx.x % ntiles;
-    const int ky = blockIdx.x / ntiles;
+    const int tile = blk % ntiles;
+    const int ky = blk / ntiles;
     const int kx0 = tile * tk;
     const int ncol = min(tk, nh - kx0);
     cpx<T> *base = spec + (int64_t)r * 3 * A.specN + (int64_t)ky * sy + kx0;
@@ -569,7 +573,7 @@ __global__ __launch_bounds__(512) void k_fft_z_t(FftArgs A, const cpx<T> *tw, co
     double v[1] = {part};
     block_sum<1>(v, red);
     if (threadIdx.x == 0) {
-        double *P = A.partial + ((int64_t)r * A.nslots + A.slot0 + blockIdx.x) * NPART;
+        double *P = A.partial + ((int64_t)r * A.nslots + A.slot0 + blk) * NPART;
         P[0] = v[0];
 #pragma unroll
         for (int q = 1; q < 7; ++q) P[q] = 0.0;
@@ -702,7 +706,7 @@ void launch_green_forward(xfft_problem *p, Work<T> &w, const Tables<T> &tb, T *f
     }
     {
         A.slot0 = p->slots.grn0;
-        dim3 grid(green_blocks<T>(g), nrhs);
+        dim3 grid((unsigned)green_blocks<T>(g) * nrhs, 1);
         xfft_prof_mark(p, -1, s);
         if (ztmpl_size(g.n2)) {
             switch (g.n2) {

@@ -43,6 +43,7 @@ struct OpArgs {
     int n0, n1, n2;
     int64_t N, nX, nirr;
     int kz, tiles_x;
+    int tiles_xy, reg_blocks, cut_blocks;   // workgroups per right-hand side
 };
 
 template <typename T>
@@ -168,12 +169,15 @@ __global__ __launch_bounds__(256) void k_regular(OpArgs<T> A) {
     __shared__ T FB[18][TE * TE];      // structure of arrays: lanes hit consecutive banks
     __shared__ double red[4 * 7];
 
-    const int r = blockIdx.z;
+    // logical block: (rhs, z chunk, tile y, tile x), x fastest
+    const int64_t lb = xcd_remap(blockIdx.x, gridDim.x);
+    const int r = (int)(lb / A.reg_blocks), blk = (int)(lb % A.reg_blocks);
     if (!rhs_active(A, r)) return;
     const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
-    const int bx = blockIdx.x % A.tiles_x, by = blockIdx.x / A.tiles_x;
+    const int tile = blk % A.tiles_xy, zc = blk / A.tiles_xy;
+    const int bx = tile % A.tiles_x, by = tile / A.tiles_x;
     const int i0 = bx * TO, j0 = by * TO;
-    const int k0 = blockIdx.y * A.kz, k1 = min(k0 + A.kz, A.n2);
+    const int k0 = zc * A.kz, k1 = min(k0 + A.kz, A.n2);
     const int n0 = A.n0, n1 = A.n1, n2 = A.n2;
     const int64_t N = A.N, plane_sz = (int64_t)n0 * n1;
     const int a = i0 - 1 + tx, b = j0 - 1 + ty;
@@ -309,7 +313,6 @@ __global__ __launch_bounds__(256) void k_regular(OpArgs<T> A) {
     }
     block_sum<7>(acc7, red);
     if (tid == 0) {
-        const int blk = blockIdx.x + gridDim.x * blockIdx.y;
         double *P = A.partial + ((int64_t)r * A.nslots + A.slot0 + blk) * NPART;
 #pragma unroll
         for (int q = 0; q < 7; ++q) P[q] = acc7[q];
@@ -415,9 +418,10 @@ __device__ __forceinline__ void irregular_tet(const T (&Lc)[8], const T *__restr
 template <typename T, bool HX, bool EB>
 __global__ __launch_bounds__(128) void k_irregular(OpArgs<T> A) {
     __shared__ double red[2 * 7];
-    const int r = blockIdx.y;
+    const int64_t lb = xcd_remap(blockIdx.x, gridDim.x);
+    const int r = (int)(lb / A.cut_blocks), blk = (int)(lb % A.cut_blocks);
     if (!rhs_active(A, r)) return;
-    const int64_t qv = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t qv = (int64_t)blk * blockDim.x + threadIdx.x;
     double acc7[7] = {0, 0, 0, 0, 0, 0, 0};
     if (qv < A.nirr) {
         const int64_t N = A.N;
@@ -470,7 +474,7 @@ __global__ __launch_bounds__(128) void k_irregular(OpArgs<T> A) {
     }
     block_sum<7>(acc7, red);
     if (threadIdx.x == 0) {
-        double *P = A.partial + ((int64_t)r * A.nslots + A.slot0 + blockIdx.x) * NPART;
+        double *P = A.partial + ((int64_t)r * A.nslots + A.slot0 + blk) * NPART;
 #pragma unroll
         for (int q = 0; q < 7; ++q) P[q] = acc7[q];
     }
@@ -536,10 +540,11 @@ void launch_operator(xfft_problem *p, Work<T> &w, const Tables<T> &tb, const T *
     A.vstress = vstress;
     A.n0 = g.n0; A.n1 = g.n1; A.n2 = g.n2; A.N = g.N; A.nX = g.nX; A.nirr = g.nirr;
     A.kz = L.kz; A.tiles_x = L.tiles_x;
+    A.tiles_xy = L.tiles_x * L.tiles_y; A.reg_blocks = L.tiles_x * L.tiles_y * L.zchunks; A.cut_blocks = L.cut_n;
     const bool hx = x != nullptr;
     if (g.nirr > 0) {
         A.slot0 = L.cut0;
-        dim3 grid(L.cut_n, nrhs);
+        dim3 grid((unsigned)L.cut_n * nrhs, 1);
         xfft_prof_mark(p, -1, s);
         if (hx && use_ebar) k_irregular<T, true, true><<<grid, 128, 0, s>>>(A);
         else if (hx) k_irregular<T, true, false><<<grid, 128, 0, s>>>(A);
@@ -549,7 +554,7 @@ void launch_operator(xfft_problem *p, Work<T> &w, const Tables<T> &tb, const T *
     }
     {
         A.slot0 = L.fe0;
-        dim3 grid(L.tiles_x * L.tiles_y, L.zchunks, nrhs);
+        dim3 grid((unsigned)(L.tiles_x * L.tiles_y * L.zchunks) * nrhs, 1);
         xfft_prof_mark(p, -1, s);
         if (hx && use_ebar) k_regular<T, true, true, true><<<grid, 256, 0, s>>>(A);
         else if (hx && stress) k_regular<T, true, false, true><<<grid, 256, 0, s>>>(A);
