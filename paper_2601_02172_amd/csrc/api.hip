@@ -621,6 +621,8 @@ void xfft_destroy(xfft_problem *p) {
         if (q) (void)hipFree(q);
     for (int a = 0; a < 3; ++a) {
         if (p->t64.tw[a]) (void)hipFree(p->t64.tw[a]);
+        if (p->t64.tws[a]) (void)hipFree(p->t64.tws[a]);
+        if (p->t32.tws[a]) (void)hipFree(p->t32.tws[a]);
         if (p->t32.tw[a]) (void)hipFree(p->t32.tw[a]);
         if (p->t64.half[a]) (void)hipFree(p->t64.half[a]);
         if (p->t32.half[a]) (void)hipFree(p->t32.half[a]);
@@ -665,6 +667,11 @@ int xfft_setup(const int32_t n[3], const double len[3], const double *levelset, 
     xfft_problem *p = new (std::nothrow) xfft_problem();
     if (!p) return XFFT_ENOMEM;
     p->device = opt.device;
+    {
+        int ncu = 0;
+        if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, opt.device) == hipSuccess && ncu > 0)
+            p->num_cu = ncu;
+    }
     p->h = h;
     for (int a = 0; a < 3; ++a) p->len[a] = len[a];
     p->rtol = opt.rtol; p->snap_eps = opt.snap_eps; p->d0_scale = opt.d0_scale; p->inner_rtol = opt.inner_rtol;

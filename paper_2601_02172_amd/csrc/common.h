@@ -116,6 +116,7 @@ template <typename T> struct Tables {
     // (rows of uncut tets hold zeros)
     T *irr_M = nullptr;
     cpx<T> *tw[3] = {nullptr, nullptr, nullptr};   // twiddles exp(-2 pi i t / n_axis)
+    cpx<T> *tws[3] = {nullptr, nullptr, nullptr};  // stage-major twiddles of the compile-time LDS FFT
     T *half[3] = {nullptr, nullptr, nullptr};      // [n_axis][2]: sin, cos of pi k / n_axis
 };
 
@@ -174,6 +175,7 @@ struct xfft_problem {
     double h = 1.0;
     double len[3];
     int device = 0;
+    int num_cu = 256;         // compute units of the device (persistent grids)
     hipStream_t stream = nullptr;
     bool own_stream = false;
     // options

@@ -363,56 +363,44 @@ __global__ __launch_bounds__(256) void k_fft_x_inv(FftArgs A, FftPlan pl, const 
 }
 
 // ---------------------------------------------------------------- xy plane kernels (n0 == n1 == N)
-// One workgroup per (component, z plane, load).  LDS holds the whole plane; the
-// x transform runs on row pairs packed as complex lines, the y transform on the
-// kx columns.  Spectrum layout [c][ky][kz][kx] (kx fastest).
+// A workgroup transforms whole (component, z plane, load) planes held in LDS:
+// the x transform runs on row pairs packed as complex lines, the y transform on
+// the kx columns.  Spectrum layout [c][ky][kz][kx] (kx fastest).  The grid is
+// persistent (PIPE: about two workgroups per CU, each taking every gridDim-th
+// plane): the global loads of the next plane are issued into registers before
+// the current plane is transformed, so HBM traffic overlaps the LDS and ALU
+// work of the transform.  Without PIPE there is one workgroup per plane.
 template <int N> struct PlaneCfg {
     static constexpr int NH = N / 2 + 1;
     static constexpr int NP = N / 2;
     static constexpr int LS = fft_ls(N);
     static constexpr int NT = 1024;
     static constexpr int ELEMS = NH * LS;      // >= NP * LS
+    static constexpr int NIN = NP * N;         // packed row-pair elements of a plane
+    static constexpr int PE = (NIN + NT - 1) / NT;
+    static constexpr int NSP = N * NH;         // half-spectrum elements of a plane
+    static constexpr int PS = (NSP + NT - 1) / NT;
 };
 
-template <typename T> __device__ __forceinline__ bool active_of(const Flags *flags, int parity, int r) {
-    return flags == nullptr || flags[r].active[parity] != 0;
+// next plane index >= q (stride gridDim.x) of an active right-hand side
+__device__ __forceinline__ int next_plane(const FftArgs &A, int q, int per_r, int total) {
+    while (q < total && !active_rhs(A, q / per_r)) q += gridDim.x;
+    return q;
 }
 
+// LDS holds the packed row pairs of a plane: x transform, split into the two
+// real rows' spectra, transpose to kx-major lines, y transform, store.
 template <typename T, int N>
-__global__ __launch_bounds__(1024) void k_fft_plane_fwd(FftArgs A, const cpx<T> *tw, T *f, const T *z,
-                                                         cpx<T> *spec) {
+__device__ __forceinline__ void plane_forward_core(cpx<T> *sh, const cpx<T> *tw, const FftArgs &A, cpx<T> *sr,
+                                                   int kz, int tid) {
     using C = PlaneCfg<N>;
-    extern __shared__ unsigned char smem_raw[];
-    cpx<T> *sh = reinterpret_cast<cpx<T> *>(smem_raw);
-    const int r = blockIdx.y;
-    if (!active_rhs(A, r)) return;
-    const int plane = blockIdx.x;                 // c * n2 + kz
-    const int c = plane / A.n2, kz = plane - c * A.n2;
-    const T alpha = z ? (T)A.scal[r].alpha : (T)0;
-    T *fr = f + (int64_t)r * 3 * A.N + (int64_t)plane * N * N;
-    const T *zr = z ? z + (int64_t)r * 3 * A.N + (int64_t)plane * N * N : nullptr;
-    // load rows (fused residual update), pack row pairs
-    for (int idx = threadIdx.x; idx < C::NP * N; idx += C::NT) {
-        const int pp = idx / N, x = idx - pp * N;
-        const int o0 = (2 * pp) * N + x, o1 = o0 + N;
-        T a = fr[o0], b = fr[o1];
-        if (zr) {
-            a -= alpha * zr[o0];
-            b -= alpha * zr[o1];
-            fr[o0] = a;
-            fr[o1] = b;
-        }
-        sh[pp * C::LS + fft_pad(x)] = {a, b};
-    }
-    __syncthreads();
-    fft_lines<T, N, C::NP, C::NT, false>(sh, tw);
-    // split the packed spectra into the two rows; transpose to kx-major columns
+    fft_lines<T, N, C::NP, C::NT, false>(sh, tw, C::NP, tid);
     constexpr int NOUT = C::NP * C::NH;
     constexpr int MO = (NOUT + C::NT - 1) / C::NT;
     cpx<T> ra[MO], rb[MO];
 #pragma unroll
     for (int i = 0; i < MO; ++i) {
-        const int idx = threadIdx.x + i * C::NT;
+        const int idx = tid + i * C::NT;
         if (idx < NOUT) {
             const int pp = idx / C::NH, kx = idx - pp * C::NH;
             const cpx<T> Zk = sh[pp * C::LS + fft_pad(kx)];
@@ -424,7 +412,7 @@ __global__ __launch_bounds__(1024) void k_fft_plane_fwd(FftArgs A, const cpx<T> 
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < MO; ++i) {
-        const int idx = threadIdx.x + i * C::NT;
+        const int idx = tid + i * C::NT;
         if (idx < NOUT) {
             const int pp = idx / C::NH, kx = idx - pp * C::NH;
             sh[kx * C::LS + fft_pad(2 * pp)] = ra[i];
@@ -432,38 +420,93 @@ __global__ __launch_bounds__(1024) void k_fft_plane_fwd(FftArgs A, const cpx<T> 
         }
     }
     __syncthreads();
-    fft_lines<T, N, C::NH, C::NT, false>(sh, tw);
-    cpx<T> *sr = spec + (int64_t)r * 3 * A.specN + (int64_t)c * A.specN;
-    for (int idx = threadIdx.x; idx < N * C::NH; idx += C::NT) {
+    fft_lines<T, N, C::NH, C::NT, false>(sh, tw, C::NH, tid);
+    for (int idx = tid; idx < N * C::NH; idx += C::NT) {
         const int ky = idx / C::NH, kx = idx - ky * C::NH;
         sr[((int64_t)ky * A.n2 + kz) * C::NH + kx] = sh[kx * C::LS + fft_pad(ky)];
     }
 }
 
-template <typename T, int N>
-__global__ __launch_bounds__(1024) void k_fft_plane_inv(FftArgs A, const cpx<T> *tw, const cpx<T> *spec, int mode,
-                                                         T *out, T *u, T *d) {
+template <typename T, int N, bool PIPE>
+__global__ __launch_bounds__(1024) void k_fft_plane_fwd(FftArgs A, const cpx<T> *tw, T *f, const T *z,
+                                                         cpx<T> *spec, int nrhs) {
     using C = PlaneCfg<N>;
     extern __shared__ unsigned char smem_raw[];
     cpx<T> *sh = reinterpret_cast<cpx<T> *>(smem_raw);
-    const int r = blockIdx.y;
-    if (!active_rhs(A, r)) return;
-    const int plane = blockIdx.x;
-    const int c = plane / A.n2, kz = plane - c * A.n2;
-    const cpx<T> *sr = spec + (int64_t)r * 3 * A.specN + (int64_t)c * A.specN;
-    for (int idx = threadIdx.x; idx < N * C::NH; idx += C::NT) {
-        const int ky = idx / C::NH, kx = idx - ky * C::NH;
-        sh[kx * C::LS + fft_pad(ky)] = sr[((int64_t)ky * A.n2 + kz) * C::NH + kx];
+    const int per_r = 3 * A.n2, total = per_r * nrhs;
+    int tid = threadIdx.x;
+    T va[C::PE], vb[C::PE], wa[C::PE], wb[C::PE];
+    auto fetch = [&](int q) {
+        const int r = q / per_r, plane = q - r * per_r;
+        const T *fr = f + (int64_t)r * 3 * A.N + (int64_t)plane * N * N;
+        const T *zr = z ? z + (int64_t)r * 3 * A.N + (int64_t)plane * N * N : nullptr;
+#pragma unroll
+        for (int i = 0; i < C::PE; ++i) {
+            const int idx = tid + i * C::NT;
+            if (C::NIN % C::NT == 0 || idx < C::NIN) {
+                const int pp = idx / N, x = idx - pp * N;
+                const int o0 = (2 * pp) * N + x;
+                va[i] = fr[o0];
+                vb[i] = fr[o0 + N];
+                if (zr) { wa[i] = zr[o0]; wb[i] = zr[o0 + N]; }
+            }
+        }
+    };
+    int q = PIPE ? next_plane(A, blockIdx.x, per_r, total) : (int)blockIdx.x;
+    if (!PIPE && !active_rhs(A, q / per_r)) return;
+    if (q < total) fetch(q);      // a persistent workgroup may have no active plane at all
+    while (q < total) {
+        // index arithmetic is recomputed per plane instead of being kept live
+        // in registers across the whole loop
+        asm volatile("" : "+v"(tid));
+        const int r = q / per_r, plane = q - r * per_r;
+        const int c = plane / A.n2, kz = plane - c * A.n2;
+        T *fr = f + (int64_t)r * 3 * A.N + (int64_t)plane * N * N;
+        const T alpha = z ? (T)A.scal[r].alpha : (T)0;
+        // fused residual update f -= alpha z; pack row pairs
+#pragma unroll
+        for (int i = 0; i < C::PE; ++i) {
+            const int idx = tid + i * C::NT;
+            if (C::NIN % C::NT == 0 || idx < C::NIN) {
+                const int pp = idx / N, x = idx - pp * N;
+                const int o0 = (2 * pp) * N + x;
+                T a = va[i], b = vb[i];
+                if (z) {
+                    a -= alpha * wa[i];
+                    b -= alpha * wb[i];
+                    fr[o0] = a;
+                    fr[o0 + N] = b;
+                }
+                sh[pp * C::LS + fft_pad(x)] = {a, b};
+            }
+        }
+        if constexpr (!PIPE) {
+            __syncthreads();
+            plane_forward_core<T, N>(sh, tw, A, spec + (int64_t)r * 3 * A.specN + (int64_t)c * A.specN, kz, tid);
+            return;
+        } else {
+            const int qn = next_plane(A, q + gridDim.x, per_r, total);
+            if (qn < total) fetch(qn);
+            __syncthreads();
+            plane_forward_core<T, N>(sh, tw, A, spec + (int64_t)r * 3 * A.specN + (int64_t)c * A.specN, kz, tid);
+            __syncthreads();
+            q = qn;
+        }
     }
-    __syncthreads();
-    fft_lines<T, N, C::NH, C::NT, true>(sh, tw);
-    // rebuild packed row pairs Z_k = A_k + i B_k over the full x spectrum
+}
+
+// LDS holds the kx-major half spectrum of a plane: y inverse transform,
+// rebuild the packed row pairs, x inverse transform.
+template <typename T, int N>
+__device__ __forceinline__ void plane_inverse_core(cpx<T> *sh, const cpx<T> *tw, int tid) {
+    using C = PlaneCfg<N>;
+    fft_lines<T, N, C::NH, C::NT, true>(sh, tw, C::NH, tid);
     constexpr int NOUT = C::NP * N;
     constexpr int MO = (NOUT + C::NT - 1) / C::NT;
     cpx<T> rz[MO];
 #pragma unroll
     for (int i = 0; i < MO; ++i) {
-        const int idx = threadIdx.x + i * C::NT;
+        const int idx = tid + i * C::NT;
         if (idx < NOUT) {
             const int pp = idx / N, k = idx - pp * N;
             const bool lo = k < C::NH;
@@ -476,107 +519,232 @@ __global__ __launch_bounds__(1024) void k_fft_plane_inv(FftArgs A, const cpx<T> 
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < MO; ++i) {
-        const int idx = threadIdx.x + i * C::NT;
+        const int idx = tid + i * C::NT;
         if (idx < NOUT) {
             const int pp = idx / N, k = idx - pp * N;
             sh[pp * C::LS + fft_pad(k)] = rz[i];
         }
     }
     __syncthreads();
-    fft_lines<T, N, C::NP, C::NT, true>(sh, tw);
-    const int64_t base = (int64_t)r * 3 * A.N + (int64_t)plane * N * N;
-    T alpha = 0, beta = 0;
-    if (mode == 1) { alpha = (T)A.scal[r].alpha; beta = (T)A.scal[r].beta; }
-    for (int idx = threadIdx.x; idx < C::NP * N; idx += C::NT) {
-        const int pp = idx / N, x = idx - pp * N;
-        const cpx<T> yv = sh[pp * C::LS + fft_pad(x)];
-        const int64_t o0 = base + (2 * pp) * N + x, o1 = o0 + N;
-        if (mode == 0) {
-            out[o0] = yv.x;
-            out[o1] = yv.y;
-        } else if (mode == 1) {
-            const T d0 = d[o0], d1 = d[o1];
-            u[o0] += alpha * d0;
-            u[o1] += alpha * d1;
-            d[o0] = yv.x + beta * d0;
-            d[o1] = yv.y + beta * d1;
-        } else {
-            d[o0] = yv.x;
-            d[o1] = yv.y;
+    fft_lines<T, N, C::NP, C::NT, true>(sh, tw, C::NP, tid);
+}
+
+// mode 0: out = G f; mode 1: u += alpha d, d = G f + beta d; mode 2: d = G f
+template <typename T, int N, bool PIPE>
+__global__ __launch_bounds__(1024) void k_fft_plane_inv(FftArgs A, const cpx<T> *tw, const cpx<T> *spec, int mode,
+                                                         T *out, T *u, T *d, int nrhs) {
+    using C = PlaneCfg<N>;
+    extern __shared__ unsigned char smem_raw[];
+    cpx<T> *sh = reinterpret_cast<cpx<T> *>(smem_raw);
+    const int per_r = 3 * A.n2, total = per_r * nrhs;
+    int tid = threadIdx.x;
+    cpx<T> sp[C::PS];
+    auto fetch = [&](int q) {
+        const int r = q / per_r, plane = q - r * per_r;
+        const int c = plane / A.n2, kz = plane - c * A.n2;
+        const cpx<T> *sr = spec + (int64_t)r * 3 * A.specN + (int64_t)c * A.specN;
+#pragma unroll
+        for (int i = 0; i < C::PS; ++i) {
+            const int idx = tid + i * C::NT;
+            if (C::NSP % C::NT == 0 || idx < C::NSP) {
+                const int ky = idx / C::NH, kx = idx - ky * C::NH;
+                sp[i] = sr[((int64_t)ky * A.n2 + kz) * C::NH + kx];
+            }
         }
+    };
+    int q = PIPE ? next_plane(A, blockIdx.x, per_r, total) : (int)blockIdx.x;
+    if (!PIPE && !active_rhs(A, q / per_r)) return;
+    if (q < total) fetch(q);      // a persistent workgroup may have no active plane at all
+    while (q < total) {
+        // index arithmetic is recomputed per plane instead of being kept live
+        // in registers across the whole loop
+        asm volatile("" : "+v"(tid));
+        const int r = q / per_r, plane = q - r * per_r;
+#pragma unroll
+        for (int i = 0; i < C::PS; ++i) {
+            const int idx = tid + i * C::NT;
+            if (C::NSP % C::NT == 0 || idx < C::NSP) {
+                const int ky = idx / C::NH, kx = idx - ky * C::NH;
+                sh[kx * C::LS + fft_pad(ky)] = sp[i];
+            }
+        }
+        const int64_t base = (int64_t)r * 3 * A.N + (int64_t)plane * N * N;
+        // PIPE: the CG update's loads of d and u of this plane are issued now,
+        // with those of the next plane's spectrum, ahead of the transform
+        T da[C::PE], db[C::PE], ua[C::PE], ub[C::PE];
+        int qn = total;
+        if constexpr (PIPE) {
+            if (mode == 1) {
+#pragma unroll
+                for (int i = 0; i < C::PE; ++i) {
+                    const int idx = tid + i * C::NT;
+                    if (C::NIN % C::NT == 0 || idx < C::NIN) {
+                        const int pp = idx / N, x = idx - pp * N;
+                        const int64_t o0 = base + (2 * pp) * N + x;
+                        da[i] = d[o0]; db[i] = d[o0 + N];
+                        ua[i] = u[o0]; ub[i] = u[o0 + N];
+                    }
+                }
+            }
+            qn = next_plane(A, q + gridDim.x, per_r, total);
+            if (qn < total) fetch(qn);
+        }
+        __syncthreads();
+        plane_inverse_core<T, N>(sh, tw, tid);
+        T alpha = 0, beta = 0;
+        if (mode == 1) { alpha = (T)A.scal[r].alpha; beta = (T)A.scal[r].beta; }
+#pragma unroll
+        for (int i = 0; i < C::PE; ++i) {
+            const int idx = tid + i * C::NT;
+            if (C::NIN % C::NT == 0 || idx < C::NIN) {
+                const int pp = idx / N, x = idx - pp * N;
+                const cpx<T> yv = sh[pp * C::LS + fft_pad(x)];
+                const int64_t o0 = base + (2 * pp) * N + x, o1 = o0 + N;
+                if (mode == 0) {
+                    out[o0] = yv.x;
+                    out[o1] = yv.y;
+                } else if (mode == 1) {
+                    T d0, d1, u0, u1;
+                    if constexpr (PIPE) {
+                        d0 = da[i]; d1 = db[i]; u0 = ua[i]; u1 = ub[i];
+                    } else {
+                        d0 = d[o0]; d1 = d[o1]; u0 = u[o0]; u1 = u[o1];
+                    }
+                    u[o0] = u0 + alpha * d0;
+                    u[o1] = u1 + alpha * d1;
+                    d[o0] = yv.x + beta * d0;
+                    d[o1] = yv.y + beta * d1;
+                } else {
+                    d[o0] = yv.x;
+                    d[o1] = yv.y;
+                }
+            }
+        }
+        if constexpr (!PIPE) return;
+        __syncthreads();
+        q = qn;
     }
 }
 
 // ---------------------------------------------------------------- z pass, compile-time length
 // Element (c, kz, ky, kx) of the spectrum at c * specN + kz * sz + ky * sy + kx.
-// One workgroup per (ky, run of tk kx columns, load); the ceil(nh / TK) runs
-// share the nh columns evenly (tk <= TK), so no run is mostly padding.  LDS
-// line c * tk + kl holds component c of column kx0 + kl.
-template <typename T, int N2, int TK>
+// Work item = (ky, run of tk kx columns, load); the ceil(nh / TK) runs share
+// the nh columns evenly (tk <= TK), so no run is mostly padding.  LDS line
+// c * tk + kl holds component c of column kx0 + kl.  Items of the active loads
+// are numbered so that every XCD takes one contiguous range (neighbouring runs
+// share cache lines).  PIPE: persistent grid (a multiple of 8 workgroups), the
+// next item's loads are issued into registers before the current item is
+// transformed; otherwise one workgroup per item.
+template <typename T, int N2, int TK, bool PIPE>
 __global__ __launch_bounds__(512) void k_fft_z_t(FftArgs A, const cpx<T> *tw, const T *h0, const T *h1,
-                                                  const T *h2, cpx<T> *spec, int64_t sz, int64_t sy) {
+                                                  const T *h2, cpx<T> *spec, int64_t sz, int64_t sy, int nrhs) {
     constexpr int LS = fft_ls(N2);
     constexpr int NL = 3 * TK;
+    constexpr int NE = NL * N2;                     // staged elements of an item
+    constexpr int PZ = (NE + 511) / 512;
     extern __shared__ unsigned char smem_raw[];
     cpx<T> *sh = reinterpret_cast<cpx<T> *>(smem_raw);
     __shared__ double red[8];
     const int nh = A.nh;
     const int ntiles = (nh + TK - 1) / TK;
-    const int nblk = A.n1 * ntiles;                 // workgroups per right-hand side
-    const int64_t lb = xcd_remap(blockIdx.x, gridDim.x);
-    const int r = (int)(lb / nblk), blk = (int)(lb % nblk);
-    if (!active_rhs(A, r)) return;
+    const int nblk = A.n1 * ntiles;                 // items per right-hand side
     const int tk = (nh + ntiles - 1) / ntiles;
-    const int tile = blk % ntiles;
-    const int ky = blk / ntiles;
-    const int kx0 = tile * tk;
-    const int ncol = min(tk, nh - kx0);
-    cpx<T> *base = spec + (int64_t)r * 3 * A.specN + (int64_t)ky * sy + kx0;
-    for (int idx = threadIdx.x; idx < NL * N2; idx += 512) {
-        const int kl = idx % TK, rest = idx / TK;
-        const int zz = rest % N2, c = rest / N2;
-        if (kl < tk)
-            sh[(c * tk + kl) * LS + fft_pad(zz)] = kl < ncol ? base[(int64_t)c * A.specN + zz * sz + kl] : cpx<T>{0, 0};
-    }
-    __syncthreads();
-    fft_lines<T, N2, NL, 512, false>(sh, tw, 3 * tk);
-    double part = 0.0;
-    const T scale = (T)(1.0 / ((double)A.n0 * (double)A.n1 * (double)N2));
-    for (int idx = threadIdx.x; idx < TK * N2; idx += 512) {
-        const int kl = idx % TK, zz = idx / TK;
-        const int kx = kx0 + kl;
-        if (kl < ncol) {
-            cpx<T> fv[3];
+    int nact = 0;
+    for (int r = 0; r < nrhs; ++r) nact += active_rhs(A, r) ? 1 : 0;
+    const int64_t total = (int64_t)nact * nblk;
+    auto item = [&](int64_t v, int &r, int &blk) {
+        const int64_t L = xcd_remap(v, total);
+        int ka = (int)(L / nblk);
+        blk = (int)(L % nblk);
+        r = 0;
+        while (!active_rhs(A, r) || ka-- > 0) ++r;  // the ka-th active load
+    };
+    int tid = threadIdx.x;
+    cpx<T> pre[PZ];
+    auto fetch = [&](int r, int blk) {
+        const int tile = blk % ntiles, ky = blk / ntiles;
+        const int kx0 = tile * tk, ncol = min(tk, nh - kx0);
+        const cpx<T> *base = spec + (int64_t)r * 3 * A.specN + (int64_t)ky * sy + kx0;
 #pragma unroll
-            for (int c = 0; c < 3; ++c) fv[c] = sh[(c * tk + kl) * LS + fft_pad(zz)];
-            const cpx<T> f0[3] = {fv[0], fv[1], fv[2]};
-            green_apply<T>(h0[2 * kx], h0[2 * kx + 1], h1[2 * ky], h1[2 * ky + 1], h2[2 * zz], h2[2 * zz + 1], fv,
-                           kx == 0 && ky == 0 && zz == 0);
-            double q = 0.0;
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                fv[c].x *= scale;
-                fv[c].y *= scale;
-                q += (double)f0[c].x * (double)fv[c].x + (double)f0[c].y * (double)fv[c].y;
-                sh[(c * tk + kl) * LS + fft_pad(zz)] = fv[c];
+        for (int j = 0; j < PZ; ++j) {
+            const int idx = tid + j * 512;
+            if (NE % 512 == 0 || idx < NE) {
+                const int kl = idx % TK, rest = idx / TK;
+                const int zz = rest % N2, c = rest / N2;
+                pre[j] = kl < ncol ? base[(int64_t)c * A.specN + zz * sz + kl] : cpx<T>{0, 0};
             }
-            part += ((kx == 0 || 2 * kx == A.n0) ? 1.0 : 2.0) * q;
         }
+    };
+    int64_t v = blockIdx.x;
+    int r = 0, blk = 0;
+    if (v < total) {
+        item(v, r, blk);
+        fetch(r, blk);
     }
-    __syncthreads();
-    fft_lines<T, N2, NL, 512, true>(sh, tw, 3 * tk);
-    for (int idx = threadIdx.x; idx < NL * N2; idx += 512) {
-        const int kl = idx % TK, rest = idx / TK;
-        const int zz = rest % N2, c = rest / N2;
-        if (kl < ncol) base[(int64_t)c * A.specN + zz * sz + kl] = sh[(c * tk + kl) * LS + fft_pad(zz)];
-    }
-    double v[1] = {part};
-    block_sum<1>(v, red);
-    if (threadIdx.x == 0) {
-        double *P = A.partial + ((int64_t)r * A.nslots + A.slot0 + blk) * NPART;
-        P[0] = v[0];
+    while (v < total) {
+        asm volatile("" : "+v"(tid));   // recompute index arithmetic per item
+        const int tile = blk % ntiles, ky = blk / ntiles;
+        const int kx0 = tile * tk, ncol = min(tk, nh - kx0);
+        cpx<T> *base = spec + (int64_t)r * 3 * A.specN + (int64_t)ky * sy + kx0;
 #pragma unroll
-        for (int q = 1; q < 7; ++q) P[q] = 0.0;
+        for (int j = 0; j < PZ; ++j) {
+            const int idx = tid + j * 512;
+            if (NE % 512 == 0 || idx < NE) {
+                const int kl = idx % TK, rest = idx / TK;
+                const int zz = rest % N2, c = rest / N2;
+                if (kl < tk) sh[(c * tk + kl) * LS + fft_pad(zz)] = pre[j];
+            }
+        }
+        const int64_t vn = PIPE ? v + gridDim.x : total;
+        int rn = 0, bn = 0;
+        if (PIPE && vn < total) {
+            item(vn, rn, bn);
+            fetch(rn, bn);
+        }
+        __syncthreads();
+        fft_lines<T, N2, NL, 512, false>(sh, tw, 3 * tk, tid);
+        double part = 0.0;
+        const T scale = (T)(1.0 / ((double)A.n0 * (double)A.n1 * (double)N2));
+        for (int idx = tid; idx < TK * N2; idx += 512) {
+            const int kl = idx % TK, zz = idx / TK;
+            const int kx = kx0 + kl;
+            if (kl < ncol) {
+                cpx<T> fv[3];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) fv[c] = sh[(c * tk + kl) * LS + fft_pad(zz)];
+                const cpx<T> f0[3] = {fv[0], fv[1], fv[2]};
+                green_apply<T>(h0[2 * kx], h0[2 * kx + 1], h1[2 * ky], h1[2 * ky + 1], h2[2 * zz], h2[2 * zz + 1],
+                               fv, kx == 0 && ky == 0 && zz == 0);
+                double q = 0.0;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    fv[c].x *= scale;
+                    fv[c].y *= scale;
+                    q += (double)f0[c].x * (double)fv[c].x + (double)f0[c].y * (double)fv[c].y;
+                    sh[(c * tk + kl) * LS + fft_pad(zz)] = fv[c];
+                }
+                part += ((kx == 0 || 2 * kx == A.n0) ? 1.0 : 2.0) * q;
+            }
+        }
+        __syncthreads();
+        fft_lines<T, N2, NL, 512, true>(sh, tw, 3 * tk, tid);
+        for (int idx = tid; idx < NE; idx += 512) {
+            const int kl = idx % TK, rest = idx / TK;
+            const int zz = rest % N2, c = rest / N2;
+            if (kl < ncol) base[(int64_t)c * A.specN + zz * sz + kl] = sh[(c * tk + kl) * LS + fft_pad(zz)];
+        }
+        double pv[1] = {part};
+        block_sum<1>(pv, red);
+        if (tid == 0) {
+            double *P = A.partial + ((int64_t)r * A.nslots + A.slot0 + blk) * NPART;
+            P[0] = pv[0];
+#pragma unroll
+            for (int q = 1; q < 7; ++q) P[q] = 0.0;
+        }
+        __syncthreads();
+        v = vn;
+        r = rn;
+        blk = bn;
     }
 }
 
@@ -638,28 +806,54 @@ template <typename K> static void allow_lds(K kernel, size_t bytes) {
     if (bytes > 65536) (void)hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
+// pipelined persistent grid for FP32 (the FP64 variant would need more
+// registers than 1024-thread workgroups allow)
+template <typename T> static constexpr bool plane_pipe() { return sizeof(T) == 4; }
+template <typename T> static unsigned plane_grid(const xfft_problem *p, int nrhs) {
+    const int total = 3 * p->g.n2 * nrhs;
+    if (!plane_pipe<T>()) return (unsigned)total;
+    const int g = 2 * p->num_cu;
+    return (unsigned)(total < g ? total : g);
+}
+
 template <typename T, int N>
-static void plane_fwd(FftArgs A, dim3 grid, hipStream_t s, const cpx<T> *tw, T *f, const T *z, cpx<T> *spec) {
+static void plane_fwd(const xfft_problem *p, FftArgs A, int nrhs, hipStream_t s, const cpx<T> *tw, T *f,
+                      const T *z, cpx<T> *spec) {
+    constexpr bool PIPE = plane_pipe<T>();
     const size_t lds = (size_t)PlaneCfg<N>::ELEMS * sizeof(cpx<T>);
     static bool init = false;
-    if (!init) { allow_lds(k_fft_plane_fwd<T, N>, lds); init = true; }
-    k_fft_plane_fwd<T, N><<<grid, PlaneCfg<N>::NT, lds, s>>>(A, tw, f, z, spec);
+    if (!init) { allow_lds(k_fft_plane_fwd<T, N, PIPE>, lds); init = true; }
+    k_fft_plane_fwd<T, N, PIPE><<<plane_grid<T>(p, nrhs), PlaneCfg<N>::NT, lds, s>>>(A, tw, f, z, spec, nrhs);
 }
 template <typename T, int N>
-static void plane_inv(FftArgs A, dim3 grid, hipStream_t s, const cpx<T> *tw, const cpx<T> *spec, int mode, T *out,
-                      T *u, T *d) {
+static void plane_inv(const xfft_problem *p, FftArgs A, int nrhs, hipStream_t s, const cpx<T> *tw,
+                      const cpx<T> *spec, int mode, T *out, T *u, T *d) {
+    constexpr bool PIPE = plane_pipe<T>();
     const size_t lds = (size_t)PlaneCfg<N>::ELEMS * sizeof(cpx<T>);
     static bool init = false;
-    if (!init) { allow_lds(k_fft_plane_inv<T, N>, lds); init = true; }
-    k_fft_plane_inv<T, N><<<grid, PlaneCfg<N>::NT, lds, s>>>(A, tw, spec, mode, out, u, d);
+    if (!init) { allow_lds(k_fft_plane_inv<T, N, PIPE>, lds); init = true; }
+    k_fft_plane_inv<T, N, PIPE><<<plane_grid<T>(p, nrhs), PlaneCfg<N>::NT, lds, s>>>(A, tw, spec, mode, out, u, d,
+                                                                                     nrhs);
 }
 template <typename T, int N2>
-static void zpass(FftArgs A, dim3 grid, hipStream_t s, const Tables<T> &tb, cpx<T> *spec, int64_t sz, int64_t sy) {
+static void zpass(const xfft_problem *p, FftArgs A, int nrhs, hipStream_t s, const Tables<T> &tb, cpx<T> *spec,
+                  int64_t sz, int64_t sy) {
     constexpr int TK = tkz_t<T>();
+    constexpr bool PIPE = false;
     const size_t lds = (size_t)3 * TK * fft_ls(N2) * sizeof(cpx<T>);
     static bool init = false;
-    if (!init) { allow_lds(k_fft_z_t<T, N2, TK>, lds); init = true; }
-    k_fft_z_t<T, N2, TK><<<grid, 512, lds, s>>>(A, tb.tw[2], tb.half[0], tb.half[1], tb.half[2], spec, sz, sy);
+    if (!init) { allow_lds(k_fft_z_t<T, N2, TK, PIPE>, lds); init = true; }
+    const int64_t items = (int64_t)green_blocks<T>(p->g) * nrhs;
+    int64_t grid = items;
+    if (PIPE) {
+        int per_cu = (int)((160 * 1024) / (lds + 64));
+        if (per_cu > 4) per_cu = 4;                 // 8 waves each, 32 per CU
+        if (per_cu < 1) per_cu = 1;
+        const int64_t g = (int64_t)per_cu * p->num_cu / 8 * 8;
+        if (g >= 8 && g < grid) grid = g;
+    }
+    k_fft_z_t<T, N2, TK, PIPE><<<(unsigned)grid, 512, lds, s>>>(A, tb.tws[2], tb.half[0], tb.half[1], tb.half[2], spec,
+                                                               sz, sy, nrhs);
 }
 
 template <typename T>
@@ -672,15 +866,14 @@ void launch_green_forward(xfft_problem *p, Work<T> &w, const Tables<T> &tb, T *f
     if (plane) {
         sz = g.nh;
         sy = (int64_t)g.n2 * g.nh;
-        dim3 grid(3 * g.n2, nrhs);
         xfft_prof_mark(p, -1, s);
         switch (g.n0) {
-            case 16: plane_fwd<T, 16>(A, grid, s, tb.tw[0], f, z, w.spec); break;
-            case 32: plane_fwd<T, 32>(A, grid, s, tb.tw[0], f, z, w.spec); break;
-            case 48: plane_fwd<T, 48>(A, grid, s, tb.tw[0], f, z, w.spec); break;
-            case 64: plane_fwd<T, 64>(A, grid, s, tb.tw[0], f, z, w.spec); break;
-            case 96: plane_fwd<T, 96>(A, grid, s, tb.tw[0], f, z, w.spec); break;
-            default: plane_fwd<T, 128>(A, grid, s, tb.tw[0], f, z, w.spec); break;
+            case 16: plane_fwd<T, 16>(p, A, nrhs, s, tb.tws[0], f, z, w.spec); break;
+            case 32: plane_fwd<T, 32>(p, A, nrhs, s, tb.tws[0], f, z, w.spec); break;
+            case 48: plane_fwd<T, 48>(p, A, nrhs, s, tb.tws[0], f, z, w.spec); break;
+            case 64: plane_fwd<T, 64>(p, A, nrhs, s, tb.tws[0], f, z, w.spec); break;
+            case 96: plane_fwd<T, 96>(p, A, nrhs, s, tb.tws[0], f, z, w.spec); break;
+            default: plane_fwd<T, 128>(p, A, nrhs, s, tb.tws[0], f, z, w.spec); break;
         }
         xfft_prof_mark(p, K_FFT_X_FWD + (sizeof(T) == 8 ? K_COUNT : 0), s);
     } else {
@@ -710,13 +903,13 @@ void launch_green_forward(xfft_problem *p, Work<T> &w, const Tables<T> &tb, T *f
         xfft_prof_mark(p, -1, s);
         if (ztmpl_size(g.n2)) {
             switch (g.n2) {
-                case 16: zpass<T, 16>(A, grid, s, tb, w.spec, sz, sy); break;
-                case 32: zpass<T, 32>(A, grid, s, tb, w.spec, sz, sy); break;
-                case 48: zpass<T, 48>(A, grid, s, tb, w.spec, sz, sy); break;
-                case 64: zpass<T, 64>(A, grid, s, tb, w.spec, sz, sy); break;
-                case 96: zpass<T, 96>(A, grid, s, tb, w.spec, sz, sy); break;
-                case 128: zpass<T, 128>(A, grid, s, tb, w.spec, sz, sy); break;
-                default: zpass<T, 256>(A, grid, s, tb, w.spec, sz, sy); break;
+                case 16: zpass<T, 16>(p, A, nrhs, s, tb, w.spec, sz, sy); break;
+                case 32: zpass<T, 32>(p, A, nrhs, s, tb, w.spec, sz, sy); break;
+                case 48: zpass<T, 48>(p, A, nrhs, s, tb, w.spec, sz, sy); break;
+                case 64: zpass<T, 64>(p, A, nrhs, s, tb, w.spec, sz, sy); break;
+                case 96: zpass<T, 96>(p, A, nrhs, s, tb, w.spec, sz, sy); break;
+                case 128: zpass<T, 128>(p, A, nrhs, s, tb, w.spec, sz, sy); break;
+                default: zpass<T, 256>(p, A, nrhs, s, tb, w.spec, sz, sy); break;
             }
         } else {
             const int tk = tk_z(g);
@@ -743,14 +936,13 @@ void launch_green_inverse(xfft_problem *p, Work<T> &w, const Tables<T> &tb, int 
     FftArgs A = fft_args<T>(p, flags, parity);
     xfft_prof_mark(p, -1, s);
     if (plane_path<T>(g)) {
-        dim3 grid(3 * g.n2, nrhs);
         switch (g.n0) {
-            case 16: plane_inv<T, 16>(A, grid, s, tb.tw[0], w.spec, mode, out, w.u, w.d); break;
-            case 32: plane_inv<T, 32>(A, grid, s, tb.tw[0], w.spec, mode, out, w.u, w.d); break;
-            case 48: plane_inv<T, 48>(A, grid, s, tb.tw[0], w.spec, mode, out, w.u, w.d); break;
-            case 64: plane_inv<T, 64>(A, grid, s, tb.tw[0], w.spec, mode, out, w.u, w.d); break;
-            case 96: plane_inv<T, 96>(A, grid, s, tb.tw[0], w.spec, mode, out, w.u, w.d); break;
-            default: plane_inv<T, 128>(A, grid, s, tb.tw[0], w.spec, mode, out, w.u, w.d); break;
+            case 16: plane_inv<T, 16>(p, A, nrhs, s, tb.tws[0], w.spec, mode, out, w.u, w.d); break;
+            case 32: plane_inv<T, 32>(p, A, nrhs, s, tb.tws[0], w.spec, mode, out, w.u, w.d); break;
+            case 48: plane_inv<T, 48>(p, A, nrhs, s, tb.tws[0], w.spec, mode, out, w.u, w.d); break;
+            case 64: plane_inv<T, 64>(p, A, nrhs, s, tb.tws[0], w.spec, mode, out, w.u, w.d); break;
+            case 96: plane_inv<T, 96>(p, A, nrhs, s, tb.tws[0], w.spec, mode, out, w.u, w.d); break;
+            default: plane_inv<T, 128>(p, A, nrhs, s, tb.tws[0], w.spec, mode, out, w.u, w.d); break;
         }
     } else {
         const int pp = pairs_for<T>(g.n0);

@@ -4,7 +4,7 @@
 // element after every 16 keeps the stride-R stores of the early Stockham stages
 // off a single LDS bank, and the odd line stride separates lines.  Every stage
 // a thread loads the R inputs of up to MB butterflies, applies the twiddles
-// exp(-+2 pi i r k / (Ns R)) (table tw of exp(-2 pi i t / N)), runs the
+// exp(-+2 pi i r k / (Ns R)) (stage-major table tw, see fft_stage_index), runs the
 // radix-R DFT in registers, and after a barrier stores the outputs in autosort
 // (Stockham) order; all index arithmetic is by compile-time constants.  The
 // power-of-two part uses as few stages as possible (radix 16 where that saves
@@ -37,6 +37,26 @@ __host__ __device__ constexpr int fft_radix(int n, int stage) {
     }
     while (m % 3 == 0) { m /= 3; r[ns++] = 3; }
     return stage < ns ? r[stage] : 0;
+}
+
+// Stage-major twiddle table of the compile-time plan of length n: the R - 1
+// twiddles exp(-2 pi i r k / (Ns R)), r = 1 .. R-1, of butterfly column k of
+// the stage with span Ns are contiguous at Ns - 1 + k (R - 1) + r - 1, so a
+// butterfly addresses them with one base and constant offsets.  Entry e
+// (0 <= e < n - 1) equals exp(-2 pi i t / n) with the t returned here (-1 when
+// n has no compile-time plan).
+__host__ __device__ constexpr int fft_stage_index(int n, int e) {
+    int ns = 1;
+    for (int st = 0;; ++st) {
+        const int R = fft_radix(n, st);
+        if (R == 0) return -1;
+        if (e < ns * R - 1) {
+            const int off = e - (ns - 1), k = off / (R - 1), r = off % (R - 1) + 1;
+            return r * k * (n / (ns * R));
+        }
+        ns *= R;
+        if (ns >= n) return -1;
+    }
 }
 
 // x * exp(-+2 pi i M / 16), exact for multiples of a quarter turn
@@ -131,29 +151,41 @@ __device__ __forceinline__ void dft_small(cpx<T> (&v)[16]) {
     }
 }
 
+// For power-of-two NB and NS the padded position of element e + r * M (M = NB
+// for loads, NS for stores, e the butterfly's first element) is
+// fft_pad(e) + r * M + (r * M) / 16 for every r < R, so each butterfly computes
+// one LDS address and the R accesses use constant offsets.
+template <int M> __host__ __device__ constexpr int pad_step(int r) { return r * M + ((r * M) >> 4); }
+
 template <typename T, int N, int NL, int NT, bool INV, int STAGE = 0, int NS = 1>
-__device__ __forceinline__ void fft_lines(cpx<T> *buf, const cpx<T> *__restrict__ tw, int nl = NL) {
+__device__ __forceinline__ void fft_lines(cpx<T> *buf, const cpx<T> *__restrict__ tw, int nl = NL,
+                                          int tid = threadIdx.x) {
     constexpr int R = fft_radix(N, STAGE);
     if constexpr (R != 0) {
         constexpr int LS = fft_ls(N);
         constexpr int NB = N / R;
         constexpr int TOTAL = NL * NB;
         constexpr int MB = (TOTAL + NT - 1) / NT;
-        constexpr int TWS = N / (NS * R);
+        constexpr bool P2 = (NB & (NB - 1)) == 0 && (NS & (NS - 1)) == 0;
         const int total = nl * NB;          // lines nl .. NL-1 are skipped
         cpx<T> v[MB][16];
+        int st[MB];                         // padded LDS position of each butterfly's first output
 #pragma unroll
         for (int i = 0; i < MB; ++i) {
-            const int b = threadIdx.x + i * NT;
+            const int b = tid + i * NT;
+            st[i] = 0;
             if ((TOTAL % NT == 0 && nl == NL) || b < total) {
                 const int line = b / NB, jj = b - line * NB;
                 const int k = jj % NS;
-                const cpx<T> *Lp = buf + line * LS;
+                const int base = (jj / NS) * NS * R + k;
+                const int ld = line * LS + fft_pad(jj);
+                st[i] = line * LS + fft_pad(base);
+                const cpx<T> *twk = tw + (NS - 1) + k * (R - 1) - 1;   // twk[r], r >= 1
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
-                    cpx<T> x = Lp[fft_pad(jj + r * NB)];
+                    cpx<T> x = P2 ? buf[ld + pad_step<NB>(r)] : buf[line * LS + fft_pad(jj + r * NB)];
                     if (NS > 1 && r > 0) {
-                        cpx<T> w = tw[r * k * TWS];
+                        cpx<T> w = twk[r];
                         if (INV) w.y = -w.y;
                         x = cmul(x, w);
                     }
@@ -165,18 +197,21 @@ __device__ __forceinline__ void fft_lines(cpx<T> *buf, const cpx<T> *__restrict_
         __syncthreads();
 #pragma unroll
         for (int i = 0; i < MB; ++i) {
-            const int b = threadIdx.x + i * NT;
+            const int b = tid + i * NT;
             if ((TOTAL % NT == 0 && nl == NL) || b < total) {
-                const int line = b / NB, jj = b - line * NB;
-                const int k = jj % NS;
-                cpx<T> *Lp = buf + line * LS;
-                const int base = (jj / NS) * NS * R + k;
+                if constexpr (P2) {
 #pragma unroll
-                for (int r = 0; r < R; ++r) Lp[fft_pad(base + r * NS)] = v[i][r];
+                    for (int r = 0; r < R; ++r) buf[st[i] + pad_step<NS>(r)] = v[i][r];
+                } else {
+                    const int line = b / NB, jj = b - line * NB;
+                    const int base = (jj / NS) * NS * R + jj % NS;
+#pragma unroll
+                    for (int r = 0; r < R; ++r) buf[line * LS + fft_pad(base + r * NS)] = v[i][r];
+                }
             }
         }
         __syncthreads();
-        fft_lines<T, N, NL, NT, INV, STAGE + 1, NS * R>(buf, tw, nl);
+        fft_lines<T, N, NL, NT, INV, STAGE + 1, NS * R>(buf, tw, nl, tid);
     }
 }
 

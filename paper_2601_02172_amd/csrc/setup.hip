@@ -14,6 +14,7 @@
 //  6. FFT twiddles exp(-2 pi i t / n) and half-angle tables sin, cos(pi k / n).
 #include "kernels.h"
 #include "element.h"
+#include "fft_lines.h"
 
 #include <cmath>
 #include <vector>
@@ -348,6 +349,16 @@ __global__ void k_fft_tables(int n, double2 *tw64, float2 *tw32, double *half64,
     half32[2 * t + 1] = (float)hc;
 }
 
+// stage-major twiddle tables (gathered from the natural-order ones, so the
+// values are identical)
+__global__ void k_fft_stage_tables(int n, const double2 *tw64, const float2 *tw32, double2 *st64, float2 *st32) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    const int t = e < n - 1 ? fft_stage_index(n, e) : -1;
+    st64[e] = t >= 0 ? tw64[t] : make_double2(1.0, 0.0);
+    st32[e] = t >= 0 ? tw32[t] : make_float2(1.0f, 0.0f);
+}
+
 __global__ void k_lame(int n, const double *lame, float *lame32) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t < 2 * n) lame32[t] = (float)lame[t];
@@ -485,11 +496,16 @@ int compute_tables(xfft_problem *p) {
         if (hipMalloc(&p->t64.tw[a], sizeof(cpx<double>) * n[a]) != hipSuccess ||
             hipMalloc(&p->t32.tw[a], sizeof(cpx<float>) * n[a]) != hipSuccess ||
             hipMalloc(&p->t64.half[a], sizeof(double) * 2 * n[a]) != hipSuccess ||
-            hipMalloc(&p->t32.half[a], sizeof(float) * 2 * n[a]) != hipSuccess)
+            hipMalloc(&p->t32.half[a], sizeof(float) * 2 * n[a]) != hipSuccess ||
+            hipMalloc(&p->t64.tws[a], sizeof(cpx<double>) * n[a]) != hipSuccess ||
+            hipMalloc(&p->t32.tws[a], sizeof(cpx<float>) * n[a]) != hipSuccess)
             return XFFT_ENOMEM_INTERNAL;
         k_fft_tables<<<(n[a] + 255) / 256, 256, 0, s>>>(n[a], reinterpret_cast<double2 *>(p->t64.tw[a]),
                                                         reinterpret_cast<float2 *>(p->t32.tw[a]), p->t64.half[a],
                                                         p->t32.half[a]);
+        k_fft_stage_tables<<<(n[a] + 255) / 256, 256, 0, s>>>(
+            n[a], reinterpret_cast<const double2 *>(p->t64.tw[a]), reinterpret_cast<const float2 *>(p->t32.tw[a]),
+            reinterpret_cast<double2 *>(p->t64.tws[a]), reinterpret_cast<float2 *>(p->t32.tws[a]));
     }
     const int np = p->g.nphase;
     if (hipMalloc(&p->t64.lame, sizeof(double) * 2 * np) != hipSuccess ||
