@@ -362,6 +362,147 @@ __global__ __launch_bounds__(256) void k_fft_x_inv(FftArgs A, FftPlan pl, const 
     }
 }
 
+// ---------------------------------------------------------------- x and y passes, compile-time length
+// Used when the xy plane does not fit in LDS (e.g. 256^2): the x transform on
+// PP row pairs per workgroup, the y transform on runs of kx columns; both with
+// the LDS Stockham transform of fft_lines.h.  Spectrum layout [c][kz][ky][kx].
+template <int N> struct XCfg {
+    static constexpr int NH = N / 2 + 1;
+    static constexpr int PP = 4096 / N;         // row pairs per workgroup
+    static constexpr int LS = fft_ls(N);
+};
+
+template <typename T, int N>
+__global__ __launch_bounds__(256) void k_fft_x_fwd_t(FftArgs A, const cpx<T> *tw, T *f, const T *z, cpx<T> *spec,
+                                                      int nrhs) {
+    using C = XCfg<N>;
+    extern __shared__ unsigned char smem_raw[];
+    cpx<T> *sh = reinterpret_cast<cpx<T> *>(smem_raw);
+    const int64_t npairs = (int64_t)3 * A.n2 * A.n1 / 2;
+    const int nblk = (int)((npairs + C::PP - 1) / C::PP);
+    const int64_t lb = xcd_remap(blockIdx.x, gridDim.x);
+    const int r = (int)(lb / nblk), blk = (int)(lb % nblk);
+    if (!active_rhs(A, r)) return;
+    const T alpha = z ? (T)A.scal[r].alpha : (T)0;
+    T *fr = f + (int64_t)r * 3 * A.N;
+    const T *zr = z ? z + (int64_t)r * 3 * A.N : nullptr;
+    cpx<T> *sr = spec + (int64_t)r * 3 * A.specN;
+    const int64_t p0 = (int64_t)blk * C::PP;
+    for (int idx = threadIdx.x; idx < C::PP * N; idx += 256) {
+        const int lp = idx / N, x = idx - lp * N;
+        const int64_t pr = p0 + lp;
+        T a = 0, b = 0;
+        if (pr < npairs) {
+            const int64_t o0 = (2 * pr) * N + x, o1 = o0 + N;
+            a = fr[o0];
+            b = fr[o1];
+            if (zr) {
+                a -= alpha * zr[o0];
+                b -= alpha * zr[o1];
+                fr[o0] = a;
+                fr[o1] = b;
+            }
+        }
+        sh[lp * C::LS + fft_pad(x)] = {a, b};
+    }
+    __syncthreads();
+    fft_lines<T, N, C::PP, 256, false>(sh, tw);
+    for (int idx = threadIdx.x; idx < C::PP * C::NH; idx += 256) {
+        const int lp = idx / C::NH, kx = idx - lp * C::NH;
+        const int64_t pr = p0 + lp;
+        if (pr < npairs) {
+            const cpx<T> Zk = sh[lp * C::LS + fft_pad(kx)];
+            const cpx<T> Zm = sh[lp * C::LS + fft_pad(kx == 0 ? 0 : N - kx)];
+            sr[(2 * pr) * C::NH + kx] = {(T)0.5 * (Zk.x + Zm.x), (T)0.5 * (Zk.y - Zm.y)};
+            sr[(2 * pr + 1) * C::NH + kx] = {(T)0.5 * (Zk.y + Zm.y), (T)-0.5 * (Zk.x - Zm.x)};
+        }
+    }
+}
+
+// mode 0: out = G f; mode 1: u += alpha d, d = G f + beta d; mode 2: d = G f
+template <typename T, int N>
+__global__ __launch_bounds__(256) void k_fft_x_inv_t(FftArgs A, const cpx<T> *tw, const cpx<T> *spec, int mode,
+                                                      T *out, T *u, T *d, int nrhs) {
+    using C = XCfg<N>;
+    extern __shared__ unsigned char smem_raw[];
+    cpx<T> *sh = reinterpret_cast<cpx<T> *>(smem_raw);
+    const int64_t npairs = (int64_t)3 * A.n2 * A.n1 / 2;
+    const int nblk = (int)((npairs + C::PP - 1) / C::PP);
+    const int64_t lb = xcd_remap(blockIdx.x, gridDim.x);
+    const int r = (int)(lb / nblk), blk = (int)(lb % nblk);
+    if (!active_rhs(A, r)) return;
+    const cpx<T> *sr = spec + (int64_t)r * 3 * A.specN;
+    const int64_t p0 = (int64_t)blk * C::PP;
+    for (int idx = threadIdx.x; idx < C::PP * N; idx += 256) {
+        const int lp = idx / N, k = idx - lp * N;
+        const int64_t pr = p0 + lp;
+        cpx<T> Zv = {0, 0};
+        if (pr < npairs) {
+            const bool lo = k < C::NH;
+            const int kk = lo ? k : N - k;
+            cpx<T> Av = sr[(2 * pr) * C::NH + kk], Bv = sr[(2 * pr + 1) * C::NH + kk];
+            if (!lo) { Av.y = -Av.y; Bv.y = -Bv.y; }
+            Zv = {Av.x - Bv.y, Av.y + Bv.x};
+        }
+        sh[lp * C::LS + fft_pad(k)] = Zv;
+    }
+    __syncthreads();
+    fft_lines<T, N, C::PP, 256, true>(sh, tw);
+    const int64_t rN = (int64_t)r * 3 * A.N;
+    T alpha = 0, beta = 0;
+    if (mode == 1) { alpha = (T)A.scal[r].alpha; beta = (T)A.scal[r].beta; }
+    for (int idx = threadIdx.x; idx < C::PP * N; idx += 256) {
+        const int lp = idx / N, x = idx - lp * N;
+        const int64_t pr = p0 + lp;
+        if (pr < npairs) {
+            const cpx<T> yv = sh[lp * C::LS + fft_pad(x)];
+            const int64_t o0 = rN + (2 * pr) * N + x, o1 = o0 + N;
+            if (mode == 0) {
+                out[o0] = yv.x;
+                out[o1] = yv.y;
+            } else if (mode == 1) {
+                const T d0 = d[o0], d1 = d[o1];
+                u[o0] += alpha * d0;
+                u[o1] += alpha * d1;
+                d[o0] = yv.x + beta * d0;
+                d[o1] = yv.y + beta * d1;
+            } else {
+                d[o0] = yv.x;
+                d[o1] = yv.y;
+            }
+        }
+    }
+}
+
+// y transform of runs of up to TK kx columns of one (component, kz) plane; the
+// ceil(nh / TK) runs share the nh columns evenly
+template <typename T, int N1, int TK, bool INV>
+__global__ __launch_bounds__(256) void k_fft_y_t(FftArgs A, const cpx<T> *tw, cpx<T> *spec, int nrhs) {
+    constexpr int LS = fft_ls(N1);
+    extern __shared__ unsigned char smem_raw[];
+    cpx<T> *sh = reinterpret_cast<cpx<T> *>(smem_raw);
+    const int nh = A.nh;
+    const int ntiles = (nh + TK - 1) / TK;
+    const int tk = (nh + ntiles - 1) / ntiles;
+    const int nblk = 3 * A.n2 * ntiles;
+    const int64_t lb = xcd_remap(blockIdx.x, gridDim.x);
+    const int r = (int)(lb / nblk), blk = (int)(lb % nblk);
+    if (!active_rhs(A, r)) return;
+    const int tile = blk % ntiles, plane = blk / ntiles;       // plane = c * n2 + kz
+    const int kx0 = tile * tk, ncol = min(tk, nh - kx0);
+    cpx<T> *base = spec + (int64_t)r * 3 * A.specN + (int64_t)plane * N1 * nh + kx0;
+    for (int idx = threadIdx.x; idx < TK * N1; idx += 256) {
+        const int kl = idx % TK, yy = idx / TK;
+        if (kl < tk) sh[kl * LS + fft_pad(yy)] = kl < ncol ? base[(int64_t)yy * nh + kl] : cpx<T>{0, 0};
+    }
+    __syncthreads();
+    fft_lines<T, N1, TK, 256, INV>(sh, tw, tk);
+    for (int idx = threadIdx.x; idx < TK * N1; idx += 256) {
+        const int kl = idx % TK, yy = idx / TK;
+        if (kl < ncol) base[(int64_t)yy * nh + kl] = sh[kl * LS + fft_pad(yy)];
+    }
+}
+
 // ---------------------------------------------------------------- xy plane kernels (n0 == n1 == N)
 // A workgroup transforms whole (component, z plane, load) planes held in LDS:
 // the x transform runs on row pairs packed as complex lines, the y transform on
@@ -856,6 +997,76 @@ static void zpass(const xfft_problem *p, FftArgs A, int nrhs, hipStream_t s, con
                                                                sz, sy, nrhs);
 }
 
+// compile-time x and y passes (ztmpl sizes); return false when n has no such variant
+template <typename T, int N> static void xfwd_t(const xfft_problem *p, FftArgs A, int nrhs, hipStream_t s,
+                                                const cpx<T> *tw, T *f, const T *z, cpx<T> *spec) {
+    const size_t lds = (size_t)XCfg<N>::PP * XCfg<N>::LS * sizeof(cpx<T>);
+    static bool init = false;
+    if (!init) { allow_lds(k_fft_x_fwd_t<T, N>, lds); init = true; }
+    const int64_t npairs = (int64_t)3 * p->g.n2 * p->g.n1 / 2;
+    const int64_t nblk = (npairs + XCfg<N>::PP - 1) / XCfg<N>::PP;
+    k_fft_x_fwd_t<T, N><<<(unsigned)(nblk * nrhs), 256, lds, s>>>(A, tw, f, z, spec, nrhs);
+}
+template <typename T, int N> static void xinv_t(const xfft_problem *p, FftArgs A, int nrhs, hipStream_t s,
+                                                const cpx<T> *tw, const cpx<T> *spec, int mode, T *out, T *u,
+                                                T *d) {
+    const size_t lds = (size_t)XCfg<N>::PP * XCfg<N>::LS * sizeof(cpx<T>);
+    static bool init = false;
+    if (!init) { allow_lds(k_fft_x_inv_t<T, N>, lds); init = true; }
+    const int64_t npairs = (int64_t)3 * p->g.n2 * p->g.n1 / 2;
+    const int64_t nblk = (npairs + XCfg<N>::PP - 1) / XCfg<N>::PP;
+    k_fft_x_inv_t<T, N><<<(unsigned)(nblk * nrhs), 256, lds, s>>>(A, tw, spec, mode, out, u, d, nrhs);
+}
+template <typename T, int N1, bool INV> static void ypass_t(const xfft_problem *p, FftArgs A, int nrhs,
+                                                           hipStream_t s, const cpx<T> *tw, cpx<T> *spec) {
+    constexpr int TK = 16;
+    const size_t lds = (size_t)TK * fft_ls(N1) * sizeof(cpx<T>);
+    static bool init = false;
+    if (!init) { allow_lds(k_fft_y_t<T, N1, TK, INV>, lds); init = true; }
+    const int ntiles = (p->g.nh + TK - 1) / TK;
+    const int64_t nblk = (int64_t)3 * p->g.n2 * ntiles;
+    k_fft_y_t<T, N1, TK, INV><<<(unsigned)(nblk * nrhs), 256, lds, s>>>(A, tw, spec, nrhs);
+}
+template <typename T> static bool x_forward_t(const xfft_problem *p, FftArgs A, int nrhs, hipStream_t s,
+                                              const cpx<T> *tw, T *f, const T *z, cpx<T> *spec) {
+    switch (p->g.n0) {
+        case 16: xfwd_t<T, 16>(p, A, nrhs, s, tw, f, z, spec); return true;
+        case 32: xfwd_t<T, 32>(p, A, nrhs, s, tw, f, z, spec); return true;
+        case 48: xfwd_t<T, 48>(p, A, nrhs, s, tw, f, z, spec); return true;
+        case 64: xfwd_t<T, 64>(p, A, nrhs, s, tw, f, z, spec); return true;
+        case 96: xfwd_t<T, 96>(p, A, nrhs, s, tw, f, z, spec); return true;
+        case 128: xfwd_t<T, 128>(p, A, nrhs, s, tw, f, z, spec); return true;
+        case 256: xfwd_t<T, 256>(p, A, nrhs, s, tw, f, z, spec); return true;
+        default: return false;
+    }
+}
+template <typename T> static bool x_inverse_t(const xfft_problem *p, FftArgs A, int nrhs, hipStream_t s,
+                                              const cpx<T> *tw, const cpx<T> *spec, int mode, T *out, T *u, T *d) {
+    switch (p->g.n0) {
+        case 16: xinv_t<T, 16>(p, A, nrhs, s, tw, spec, mode, out, u, d); return true;
+        case 32: xinv_t<T, 32>(p, A, nrhs, s, tw, spec, mode, out, u, d); return true;
+        case 48: xinv_t<T, 48>(p, A, nrhs, s, tw, spec, mode, out, u, d); return true;
+        case 64: xinv_t<T, 64>(p, A, nrhs, s, tw, spec, mode, out, u, d); return true;
+        case 96: xinv_t<T, 96>(p, A, nrhs, s, tw, spec, mode, out, u, d); return true;
+        case 128: xinv_t<T, 128>(p, A, nrhs, s, tw, spec, mode, out, u, d); return true;
+        case 256: xinv_t<T, 256>(p, A, nrhs, s, tw, spec, mode, out, u, d); return true;
+        default: return false;
+    }
+}
+template <typename T, bool INV> static bool y_pass_t(const xfft_problem *p, FftArgs A, int nrhs, hipStream_t s,
+                                                     const cpx<T> *tw, cpx<T> *spec) {
+    switch (p->g.n1) {
+        case 16: ypass_t<T, 16, INV>(p, A, nrhs, s, tw, spec); return true;
+        case 32: ypass_t<T, 32, INV>(p, A, nrhs, s, tw, spec); return true;
+        case 48: ypass_t<T, 48, INV>(p, A, nrhs, s, tw, spec); return true;
+        case 64: ypass_t<T, 64, INV>(p, A, nrhs, s, tw, spec); return true;
+        case 96: ypass_t<T, 96, INV>(p, A, nrhs, s, tw, spec); return true;
+        case 128: ypass_t<T, 128, INV>(p, A, nrhs, s, tw, spec); return true;
+        case 256: ypass_t<T, 256, INV>(p, A, nrhs, s, tw, spec); return true;
+        default: return false;
+    }
+}
+
 template <typename T>
 void launch_green_forward(xfft_problem *p, Work<T> &w, const Tables<T> &tb, T *f, const T *z, int nrhs,
                           const Flags *flags, int parity, hipStream_t s) {
@@ -885,7 +1096,8 @@ void launch_green_forward(xfft_problem *p, Work<T> &w, const Tables<T> &tb, T *f
             dim3 grid((unsigned)((npairs + pp - 1) / pp), nrhs);
             const size_t lds = (size_t)pp * (g.n0 + 1) * sizeof(cpx<T>);
             xfft_prof_mark(p, -1, s);
-            k_fft_x_fwd<T><<<grid, 256, lds, s>>>(A, p->plan[0], tb.tw[0], f, z, w.spec, pp);
+            if (!x_forward_t<T>(p, A, nrhs, s, tb.tws[0], f, z, w.spec))
+                k_fft_x_fwd<T><<<grid, 256, lds, s>>>(A, p->plan[0], tb.tw[0], f, z, w.spec, pp);
             xfft_prof_mark(p, K_FFT_X_FWD + (sizeof(T) == 8 ? K_COUNT : 0), s);
         }
         {
@@ -893,7 +1105,8 @@ void launch_green_forward(xfft_problem *p, Work<T> &w, const Tables<T> &tb, T *f
             dim3 grid(3 * g.n2 * ((g.nh + tk - 1) / tk), nrhs);
             const size_t lds = (size_t)tk * (g.n1 + 1) * sizeof(cpx<T>);
             xfft_prof_mark(p, -1, s);
-            k_fft_y<T, false><<<grid, 256, lds, s>>>(A, p->plan[1], tb.tw[1], w.spec, tk);
+            if (!y_pass_t<T, false>(p, A, nrhs, s, tb.tws[1], w.spec))
+                k_fft_y<T, false><<<grid, 256, lds, s>>>(A, p->plan[1], tb.tw[1], w.spec, tk);
             xfft_prof_mark(p, K_FFT_Y_FWD + (sizeof(T) == 8 ? K_COUNT : 0), s);
         }
     }
@@ -924,7 +1137,8 @@ void launch_green_forward(xfft_problem *p, Work<T> &w, const Tables<T> &tb, T *f
         dim3 grid(3 * g.n2 * ((g.nh + tk - 1) / tk), nrhs);
         const size_t lds = (size_t)tk * (g.n1 + 1) * sizeof(cpx<T>);
         xfft_prof_mark(p, -1, s);
-        k_fft_y<T, true><<<grid, 256, lds, s>>>(A, p->plan[1], tb.tw[1], w.spec, tk);
+        if (!y_pass_t<T, true>(p, A, nrhs, s, tb.tws[1], w.spec))
+            k_fft_y<T, true><<<grid, 256, lds, s>>>(A, p->plan[1], tb.tw[1], w.spec, tk);
         xfft_prof_mark(p, K_FFT_Y_INV + (sizeof(T) == 8 ? K_COUNT : 0), s);
     }
 }
@@ -949,7 +1163,8 @@ void launch_green_inverse(xfft_problem *p, Work<T> &w, const Tables<T> &tb, int 
         const int64_t npairs = (int64_t)3 * g.n2 * g.n1 / 2;
         dim3 grid((unsigned)((npairs + pp - 1) / pp), nrhs);
         const size_t lds = (size_t)pp * (g.n0 + 1) * sizeof(cpx<T>);
-        k_fft_x_inv<T><<<grid, 256, lds, s>>>(A, p->plan[0], tb.tw[0], w.spec, mode, out, w.u, w.d, pp);
+        if (!x_inverse_t<T>(p, A, nrhs, s, tb.tws[0], w.spec, mode, out, w.u, w.d))
+            k_fft_x_inv<T><<<grid, 256, lds, s>>>(A, p->plan[0], tb.tw[0], w.spec, mode, out, w.u, w.d, pp);
     }
     xfft_prof_mark(p, K_FFT_X_INV + (sizeof(T) == 8 ? K_COUNT : 0), s);
 }

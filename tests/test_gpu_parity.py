@@ -55,6 +55,16 @@ def _case(name):
     if name == "homogeneous6":
         n = (6, 6, 6)
         return n, np.ones(216), np.zeros(216, dtype=np.int32), np.array([[1.3, 0.7]])
+    if name == "spheres_32x16x48":
+        # n0 != n1: compile-time x, y and z passes instead of the xy-plane kernels
+        n = (32, 16, 48)
+        L, ph = ms.spheres_levelset(n, [np.array([9.3, 8.2, 14.7]), np.array([24.1, 7.4, 33.9])], [5.1, 4.3])
+        return n, L, ph, np.array([[0.5769231, 0.3846154], [27.77778, 41.66667], [4.0, 4.0]])
+    if name == "spheres_256x16x16":
+        # length-256 x lines (the radix-16 x 16 plan), periodic images along x
+        n = (256, 16, 16)
+        L, ph = ms.spheres_levelset(n, [np.array([37.2, 8.1, 7.6]), np.array([250.3, 7.7, 9.2])], [4.6, 5.2])
+        return n, L, ph, np.array([[0.5769231, 0.3846154], [4.0, 4.0], [27.77778, 41.66667]])
     if name == "tiny4":
         n = (4, 4, 4)
         L, ph = ms.spheres_levelset(n, [np.array([2.1, 1.9, 2.05])], [1.2])
@@ -62,7 +72,8 @@ def _case(name):
     raise KeyError(name)
 
 
-STEP_CASES = ["sphere8", "two_spheres_36x24x18", "snapped8", "coated12", "laminate110_12", "homogeneous6", "tiny4"]
+STEP_CASES = ["sphere8", "two_spheres_36x24x18", "snapped8", "coated12", "laminate110_12", "homogeneous6", "tiny4",
+              "spheres_32x16x48", "spheres_256x16x16"]
 
 _ORACLE = {}
 
