@@ -126,7 +126,7 @@ template <typename T> struct Work {
     T *u = nullptr, *f = nullptr, *d = nullptr, *z = nullptr;          // [cap][3][N]
     T *ue = nullptr, *fe = nullptr, *de = nullptr, *ze = nullptr;      // [cap][3][nX]
     cpx<T> *spec = nullptr;                                            // [cap][3][n2][n1][nh]
-    T *cutbuf = nullptr;                                               // [cap][nirr][8][6]
+    T *cutbuf = nullptr;     // [cap][2][nirr][8][3]: FE, then scaled enriched corner forces
 };
 
 // Partial-sum slot layout per right-hand side.

@@ -929,10 +929,12 @@ template <typename T> static bool plane_path(const Geometry &g) {
     return g.n0 == g.n1 && plane_size(g.n0) &&
            (size_t)(g.n0 / 2 + 1) * fft_ls(g.n0) * sizeof(cpx<T>) <= (size_t)160 * 1024;
 }
-template <typename T> static constexpr int tkz_t() { return sizeof(T) == 8 ? 8 : 16; }
+// kx columns per z-pass workgroup: 3 x TK lines of n2 complex values in LDS
+// (about 50 KB, three workgroups per CU)
+template <typename T> static constexpr int tkz_t(int n2) { return (sizeof(T) == 8 ? 8 : 16) / (n2 >= 256 ? 2 : 1); }
 
 template <typename T> int green_blocks(const Geometry &g) {
-    const int tk = ztmpl_size(g.n2) ? tkz_t<T>() : tk_z(g);
+    const int tk = ztmpl_size(g.n2) ? tkz_t<T>(g.n2) : tk_z(g);
     return g.n1 * ((g.nh + tk - 1) / tk);
 }
 template int green_blocks<double>(const Geometry &);
@@ -979,7 +981,7 @@ static void plane_inv(const xfft_problem *p, FftArgs A, int nrhs, hipStream_t s,
 template <typename T, int N2>
 static void zpass(const xfft_problem *p, FftArgs A, int nrhs, hipStream_t s, const Tables<T> &tb, cpx<T> *spec,
                   int64_t sz, int64_t sy) {
-    constexpr int TK = tkz_t<T>();
+    constexpr int TK = tkz_t<T>(N2);
     constexpr bool PIPE = false;
     const size_t lds = (size_t)3 * TK * fft_ls(N2) * sizeof(cpx<T>);
     static bool init = false;

@@ -43,7 +43,7 @@ struct OpArgs {
     int n0, n1, n2;
     int64_t N, nX, nirr;
     int kz, tiles_x;
-    int tiles_xy, reg_blocks, cut_blocks;   // workgroups per right-hand side
+    int tiles_xy, reg_blocks, cut_blocks, enr_blocks;   // workgroups per right-hand side
 };
 
 template <typename T>
@@ -270,11 +270,11 @@ __global__ __launch_bounds__(256) void k_regular(OpArgs<T> A) {
                 if (vs) store_vstress(vs, N, vox, S);
             }
         } else {
-            const T *cb = cutbuf + (int64_t)(-m - 1) * 48;
+            const T *cb = cutbuf + (int64_t)(-m - 1) * 24;
 #pragma unroll
             for (int c = 0; c < 8; ++c)
 #pragma unroll
-                for (int i = 0; i < 3; ++i) F[c][i] = cb[6 * c + i];
+                for (int i = 0; i < 3; ++i) F[c][i] = cb[3 * c + i];
         }
         // publish the corners that belong to other threads' nodes
 #pragma unroll
@@ -459,15 +459,17 @@ __global__ __launch_bounds__(128) void k_irregular(OpArgs<T> A) {
         irregular_tet<3, T, EB>(Lc, A.irr_M + qv, A.nirr, U, Q, lab, A.lame, eb, F, Fe, S);
         irregular_tet<4, T, EB>(Lc, A.irr_M + qv, A.nirr, U, Q, lab, A.lame, eb, F, Fe, S);
         irregular_tet<5, T, EB>(Lc, A.irr_M + qv, A.nirr, U, Q, lab, A.lame, eb, F, Fe, S);
-        T *cb = A.cutbuf + ((int64_t)r * A.nirr + qv) * 48;
+        // per-load buffer: FE corner forces [nirr][8][3], then scaled enriched ones [nirr][8][3]
+        T *cb = A.cutbuf + (int64_t)r * A.nirr * 48 + qv * 24;
+        T *cbe = cb + A.nirr * 24;
 #pragma unroll
         for (int c = 0; c < 8; ++c) {
-            cb[6 * c + 0] = F[c][0];
-            cb[6 * c + 1] = F[c][1];
-            cb[6 * c + 2] = F[c][2];
-            cb[6 * c + 3] = sc[c] * Fe[c][0];
-            cb[6 * c + 4] = sc[c] * Fe[c][1];
-            cb[6 * c + 5] = sc[c] * Fe[c][2];
+            cb[3 * c + 0] = F[c][0];
+            cb[3 * c + 1] = F[c][1];
+            cb[3 * c + 2] = F[c][2];
+            cbe[3 * c + 0] = sc[c] * Fe[c][0];
+            cbe[3 * c + 1] = sc[c] * Fe[c][1];
+            cbe[3 * c + 2] = sc[c] * Fe[c][2];
         }
         add_sym(acc7, S);
         if (A.vstress) store_vstress(A.vstress + (int64_t)r * 6 * N, N, vox, S);
@@ -484,9 +486,10 @@ __global__ __launch_bounds__(128) void k_irregular(OpArgs<T> A) {
 template <typename T, bool HX>
 __global__ __launch_bounds__(256) void k_enriched(OpArgs<T> A) {
     __shared__ double red[4 * 7];
-    const int r = blockIdx.y;
+    const int64_t lb = xcd_remap(blockIdx.x, gridDim.x);
+    const int r = (int)(lb / A.enr_blocks), blk = (int)(lb % A.enr_blocks);
     if (!rhs_active(A, r)) return;
-    const int64_t jn = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t jn = (int64_t)blk * blockDim.x + threadIdx.x;
     double acc7[7] = {0, 0, 0, 0, 0, 0, 0};
     if (jn < A.nX) {
         // enr_src[j][c] = 8 * (irregular voxel) + corner, or -1: the buffered
@@ -494,12 +497,12 @@ __global__ __launch_bounds__(256) void k_enriched(OpArgs<T> A) {
         const int4 s0 = reinterpret_cast<const int4 *>(A.enr_src)[2 * jn];
         const int4 s1 = reinterpret_cast<const int4 *>(A.enr_src)[2 * jn + 1];
         const int src[8] = {s0.x, s0.y, s0.z, s0.w, s1.x, s1.y, s1.z, s1.w};
-        const T *cutbuf = A.cutbuf + (int64_t)r * A.nirr * 48;
+        const T *cbe = A.cutbuf + (int64_t)r * A.nirr * 48 + A.nirr * 24;
         T s[3] = {0, 0, 0};
 #pragma unroll
         for (int c = 0; c < 8; ++c) {
             if (src[c] >= 0) {
-                const T *cb = cutbuf + (int64_t)src[c] * 6 + 3;
+                const T *cb = cbe + (int64_t)src[c] * 3;
                 s[0] += cb[0]; s[1] += cb[1]; s[2] += cb[2];
             }
         }
@@ -516,7 +519,7 @@ __global__ __launch_bounds__(256) void k_enriched(OpArgs<T> A) {
     }
     block_sum<7>(acc7, red);
     if (threadIdx.x == 0) {
-        double *P = A.partial + ((int64_t)r * A.nslots + A.slot0 + blockIdx.x) * NPART;
+        double *P = A.partial + ((int64_t)r * A.nslots + A.slot0 + blk) * NPART;
 #pragma unroll
         for (int q = 0; q < 7; ++q) P[q] = acc7[q];
     }
@@ -541,6 +544,7 @@ void launch_operator(xfft_problem *p, Work<T> &w, const Tables<T> &tb, const T *
     A.n0 = g.n0; A.n1 = g.n1; A.n2 = g.n2; A.N = g.N; A.nX = g.nX; A.nirr = g.nirr;
     A.kz = L.kz; A.tiles_x = L.tiles_x;
     A.tiles_xy = L.tiles_x * L.tiles_y; A.reg_blocks = L.tiles_x * L.tiles_y * L.zchunks; A.cut_blocks = L.cut_n;
+    A.enr_blocks = L.enr_n;
     const bool hx = x != nullptr;
     if (g.nirr > 0) {
         A.slot0 = L.cut0;
@@ -565,7 +569,7 @@ void launch_operator(xfft_problem *p, Work<T> &w, const Tables<T> &tb, const T *
     }
     if (g.nX > 0) {
         A.slot0 = L.enr0;
-        dim3 grid(L.enr_n, nrhs);
+        dim3 grid((unsigned)L.enr_n * nrhs, 1);
         xfft_prof_mark(p, -1, s);
         if (hx) k_enriched<T, true><<<grid, 256, 0, s>>>(A);
         else k_enriched<T, false><<<grid, 256, 0, s>>>(A);
