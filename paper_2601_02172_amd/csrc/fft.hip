@@ -769,90 +769,110 @@ __global__ __launch_bounds__(1024) void k_fft_plane_inv(FftArgs A, const cpx<T> 
 
 // ---------------------------------------------------------------- z pass, compile-time length
 // Element (c, kz, ky, kx) of the spectrum at c * specN + kz * sz + ky * sy + kx.
-// Work item = (ky, run of tk kx columns, load); the ceil(nh / TK) runs share
-// the nh columns evenly (tk <= TK), so no run is mostly padding.  LDS line
-// c * tk + kl holds component c of column kx0 + kl.  Items of the active loads
-// are numbered so that every XCD takes one contiguous range (neighbouring runs
-// share cache lines).  PIPE: persistent grid (a multiple of 8 workgroups), the
-// next item's loads are issued into registers before the current item is
-// transformed; otherwise one workgroup per item.
-template <typename T, int N2, int TK, bool PIPE>
+// One workgroup per (ky, run of tk kx columns, load); the ceil(nh / TK) runs
+// share the nh columns evenly (tk <= TK), so no run is mostly padding.  LDS
+// line c * tk + kl holds component c of column kx0 + kl.  Workgroups of the
+// active loads are numbered so that every XCD takes one contiguous range
+// (neighbouring runs share cache lines).  Thread (kl, z0) = (tid % TK, tid / TK)
+// handles column kl at rows z0 + m ZR (ZR = 512 / TK): when ZR divides n2 all
+// global and LDS offsets of its elements are compile-time constants added to
+// three per-thread bases.
+template <typename T, int N2, int TK>
 __global__ __launch_bounds__(512) void k_fft_z_t(FftArgs A, const cpx<T> *tw, const T *h0, const T *h1,
                                                   const T *h2, cpx<T> *spec, int64_t sz, int64_t sy, int nrhs) {
     constexpr int LS = fft_ls(N2);
     constexpr int NL = 3 * TK;
-    constexpr int NE = NL * N2;                     // staged elements of an item
-    constexpr int PZ = (NE + 511) / 512;
+    constexpr int NE = NL * N2;                     // staged elements of a workgroup
+    static_assert(512 % TK == 0, "TK must divide the workgroup");
+    constexpr int ZR = 512 / TK;
+    constexpr bool FAST = N2 % ZR == 0 && ZR % 16 == 0;
     extern __shared__ unsigned char smem_raw[];
     cpx<T> *sh = reinterpret_cast<cpx<T> *>(smem_raw);
     __shared__ double red[8];
     const int nh = A.nh;
     const int ntiles = (nh + TK - 1) / TK;
-    const int nblk = A.n1 * ntiles;                 // items per right-hand side
+    const int nblk = A.n1 * ntiles;                 // workgroups per right-hand side
     const int tk = (nh + ntiles - 1) / ntiles;
     int nact = 0;
-    for (int r = 0; r < nrhs; ++r) nact += active_rhs(A, r) ? 1 : 0;
-    const int64_t total = (int64_t)nact * nblk;
-    auto item = [&](int64_t v, int &r, int &blk) {
-        const int64_t L = xcd_remap(v, total);
-        int ka = (int)(L / nblk);
-        blk = (int)(L % nblk);
-        r = 0;
-        while (!active_rhs(A, r) || ka-- > 0) ++r;  // the ka-th active load
-    };
-    int tid = threadIdx.x;
-    cpx<T> pre[PZ];
-    auto fetch = [&](int r, int blk) {
-        const int tile = blk % ntiles, ky = blk / ntiles;
-        const int kx0 = tile * tk, ncol = min(tk, nh - kx0);
-        const cpx<T> *base = spec + (int64_t)r * 3 * A.specN + (int64_t)ky * sy + kx0;
+    for (int q = 0; q < nrhs; ++q) nact += active_rhs(A, q) ? 1 : 0;
+    const int total = nact * nblk;
+    if ((int)blockIdx.x >= total) return;
+    const int L = (int)xcd_remap(blockIdx.x, total);
+    int ka = L / nblk;
+    const int blk = L - ka * nblk;
+    int r = 0;
+    while (!active_rhs(A, r) || ka-- > 0) ++r;      // the ka-th active load
+    const int tile = blk % ntiles, ky = blk / ntiles;
+    const int kx0 = tile * tk, ncol = min(tk, nh - kx0);
+    cpx<T> *base = spec + (int64_t)r * 3 * A.specN + (int64_t)ky * sy + kx0;
+    const int tid = threadIdx.x;
+    const int kl = tid % TK, z0 = tid / TK;
+    const T scale = (T)(1.0 / ((double)A.n0 * (double)A.n1 * (double)N2));
+    double part = 0.0;
+    if constexpr (FAST) {
+        constexpr int NSW = 3 * N2 / ZR;            // sweeps over (component, row)
+        constexpr int NZ = N2 / ZR;                 // rows per thread and component
+        cpx<T> *gb = base + kl + (int64_t)z0 * sz;
+        int lb[3];
 #pragma unroll
-        for (int j = 0; j < PZ; ++j) {
-            const int idx = tid + j * 512;
-            if (NE % 512 == 0 || idx < NE) {
-                const int kl = idx % TK, rest = idx / TK;
-                const int zz = rest % N2, c = rest / N2;
-                pre[j] = kl < ncol ? base[(int64_t)c * A.specN + zz * sz + kl] : cpx<T>{0, 0};
-            }
-        }
-    };
-    int64_t v = blockIdx.x;
-    int r = 0, blk = 0;
-    if (v < total) {
-        item(v, r, blk);
-        fetch(r, blk);
-    }
-    while (v < total) {
-        asm volatile("" : "+v"(tid));   // recompute index arithmetic per item
-        const int tile = blk % ntiles, ky = blk / ntiles;
-        const int kx0 = tile * tk, ncol = min(tk, nh - kx0);
-        cpx<T> *base = spec + (int64_t)r * 3 * A.specN + (int64_t)ky * sy + kx0;
+        for (int c = 0; c < 3; ++c) lb[c] = (c * tk + kl) * LS + fft_pad(z0);
+        if (kl < tk) {
 #pragma unroll
-        for (int j = 0; j < PZ; ++j) {
-            const int idx = tid + j * 512;
-            if (NE % 512 == 0 || idx < NE) {
-                const int kl = idx % TK, rest = idx / TK;
-                const int zz = rest % N2, c = rest / N2;
-                if (kl < tk) sh[(c * tk + kl) * LS + fft_pad(zz)] = pre[j];
+            for (int m = 0; m < NSW; ++m) {
+                const int c = (m * ZR) / N2, zo = (m * ZR) % N2;
+                sh[lb[c] + zo + zo / 16] = kl < ncol ? gb[(int64_t)c * A.specN + (int64_t)zo * sz] : cpx<T>{0, 0};
             }
-        }
-        const int64_t vn = PIPE ? v + gridDim.x : total;
-        int rn = 0, bn = 0;
-        if (PIPE && vn < total) {
-            item(vn, rn, bn);
-            fetch(rn, bn);
         }
         __syncthreads();
         fft_lines<T, N2, NL, 512, false>(sh, tw, 3 * tk, tid);
-        double part = 0.0;
-        const T scale = (T)(1.0 / ((double)A.n0 * (double)A.n1 * (double)N2));
-        for (int idx = tid; idx < TK * N2; idx += 512) {
-            const int kl = idx % TK, zz = idx / TK;
+        if (kl < ncol) {
             const int kx = kx0 + kl;
-            if (kl < ncol) {
+            const T s0 = h0[2 * kx], c0 = h0[2 * kx + 1], s1 = h1[2 * ky], c1 = h1[2 * ky + 1];
+            const double wk = (kx == 0 || 2 * kx == A.n0) ? 1.0 : 2.0;
+#pragma unroll
+            for (int m = 0; m < NZ; ++m) {
+                const int zz = z0 + m * ZR, off = m * ZR + m * ZR / 16;
                 cpx<T> fv[3];
 #pragma unroll
-                for (int c = 0; c < 3; ++c) fv[c] = sh[(c * tk + kl) * LS + fft_pad(zz)];
+                for (int c = 0; c < 3; ++c) fv[c] = sh[lb[c] + off];
+                const cpx<T> f0[3] = {fv[0], fv[1], fv[2]};
+                green_apply<T>(s0, c0, s1, c1, h2[2 * zz], h2[2 * zz + 1], fv, kx == 0 && ky == 0 && zz == 0);
+                double q = 0.0;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    fv[c].x *= scale;
+                    fv[c].y *= scale;
+                    q += (double)f0[c].x * (double)fv[c].x + (double)f0[c].y * (double)fv[c].y;
+                    sh[lb[c] + off] = fv[c];
+                }
+                part += wk * q;
+            }
+        }
+        __syncthreads();
+        fft_lines<T, N2, NL, 512, true>(sh, tw, 3 * tk, tid);
+        if (kl < ncol) {
+#pragma unroll
+            for (int m = 0; m < NSW; ++m) {
+                const int c = (m * ZR) / N2, zo = (m * ZR) % N2;
+                gb[(int64_t)c * A.specN + (int64_t)zo * sz] = sh[lb[c] + zo + zo / 16];
+            }
+        }
+    } else {
+        for (int idx = tid; idx < NE; idx += 512) {
+            const int k = idx % TK, rest = idx / TK;
+            const int zz = rest % N2, c = rest / N2;
+            if (k < tk)
+                sh[(c * tk + k) * LS + fft_pad(zz)] = k < ncol ? base[(int64_t)c * A.specN + zz * sz + k] : cpx<T>{0, 0};
+        }
+        __syncthreads();
+        fft_lines<T, N2, NL, 512, false>(sh, tw, 3 * tk, tid);
+        for (int idx = tid; idx < TK * N2; idx += 512) {
+            const int k = idx % TK, zz = idx / TK;
+            const int kx = kx0 + k;
+            if (k < ncol) {
+                cpx<T> fv[3];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) fv[c] = sh[(c * tk + k) * LS + fft_pad(zz)];
                 const cpx<T> f0[3] = {fv[0], fv[1], fv[2]};
                 green_apply<T>(h0[2 * kx], h0[2 * kx + 1], h1[2 * ky], h1[2 * ky + 1], h2[2 * zz], h2[2 * zz + 1],
                                fv, kx == 0 && ky == 0 && zz == 0);
@@ -862,7 +882,7 @@ __global__ __launch_bounds__(512) void k_fft_z_t(FftArgs A, const cpx<T> *tw, co
                     fv[c].x *= scale;
                     fv[c].y *= scale;
                     q += (double)f0[c].x * (double)fv[c].x + (double)f0[c].y * (double)fv[c].y;
-                    sh[(c * tk + kl) * LS + fft_pad(zz)] = fv[c];
+                    sh[(c * tk + k) * LS + fft_pad(zz)] = fv[c];
                 }
                 part += ((kx == 0 || 2 * kx == A.n0) ? 1.0 : 2.0) * q;
             }
@@ -870,22 +890,18 @@ __global__ __launch_bounds__(512) void k_fft_z_t(FftArgs A, const cpx<T> *tw, co
         __syncthreads();
         fft_lines<T, N2, NL, 512, true>(sh, tw, 3 * tk, tid);
         for (int idx = tid; idx < NE; idx += 512) {
-            const int kl = idx % TK, rest = idx / TK;
+            const int k = idx % TK, rest = idx / TK;
             const int zz = rest % N2, c = rest / N2;
-            if (kl < ncol) base[(int64_t)c * A.specN + zz * sz + kl] = sh[(c * tk + kl) * LS + fft_pad(zz)];
+            if (k < ncol) base[(int64_t)c * A.specN + zz * sz + k] = sh[(c * tk + k) * LS + fft_pad(zz)];
         }
-        double pv[1] = {part};
-        block_sum<1>(pv, red);
-        if (tid == 0) {
-            double *P = A.partial + ((int64_t)r * A.nslots + A.slot0 + blk) * NPART;
-            P[0] = pv[0];
+    }
+    double pv[1] = {part};
+    block_sum<1>(pv, red);
+    if (tid == 0) {
+        double *P = A.partial + ((int64_t)r * A.nslots + A.slot0 + blk) * NPART;
+        P[0] = pv[0];
 #pragma unroll
-            for (int q = 1; q < 7; ++q) P[q] = 0.0;
-        }
-        __syncthreads();
-        v = vn;
-        r = rn;
-        blk = bn;
+        for (int q = 1; q < 7; ++q) P[q] = 0.0;
     }
 }
 
@@ -982,21 +998,12 @@ template <typename T, int N2>
 static void zpass(const xfft_problem *p, FftArgs A, int nrhs, hipStream_t s, const Tables<T> &tb, cpx<T> *spec,
                   int64_t sz, int64_t sy) {
     constexpr int TK = tkz_t<T>(N2);
-    constexpr bool PIPE = false;
     const size_t lds = (size_t)3 * TK * fft_ls(N2) * sizeof(cpx<T>);
     static bool init = false;
-    if (!init) { allow_lds(k_fft_z_t<T, N2, TK, PIPE>, lds); init = true; }
-    const int64_t items = (int64_t)green_blocks<T>(p->g) * nrhs;
-    int64_t grid = items;
-    if (PIPE) {
-        int per_cu = (int)((160 * 1024) / (lds + 64));
-        if (per_cu > 4) per_cu = 4;                 // 8 waves each, 32 per CU
-        if (per_cu < 1) per_cu = 1;
-        const int64_t g = (int64_t)per_cu * p->num_cu / 8 * 8;
-        if (g >= 8 && g < grid) grid = g;
-    }
-    k_fft_z_t<T, N2, TK, PIPE><<<(unsigned)grid, 512, lds, s>>>(A, tb.tws[2], tb.half[0], tb.half[1], tb.half[2], spec,
-                                                               sz, sy, nrhs);
+    if (!init) { allow_lds(k_fft_z_t<T, N2, TK>, lds); init = true; }
+    const int64_t grid = (int64_t)green_blocks<T>(p->g) * nrhs;
+    k_fft_z_t<T, N2, TK><<<(unsigned)grid, 512, lds, s>>>(A, tb.tws[2], tb.half[0], tb.half[1], tb.half[2], spec,
+                                                        sz, sy, nrhs);
 }
 
 // compile-time x and y passes (ztmpl sizes); return false when n has no such variant
