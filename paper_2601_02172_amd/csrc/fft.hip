@@ -521,6 +521,15 @@ template <int N> struct PlaneCfg {
     static constexpr int PE = (NIN + NT - 1) / NT;
     static constexpr int NSP = N * NH;         // half-spectrum elements of a plane
     static constexpr int PS = (NSP + NT - 1) / NT;
+    // N = 64, 128: thread (kxl, kyl) = (tid % KW, tid / KW) handles columns
+    // kx = kxl < KW at rows kyl + RS m (the Nyquist column kx = KW by threads
+    // tid < N), so that all LDS offsets are per-thread bases plus compile-time
+    // constants and no index is divided by NH
+    static constexpr int KW = N / 2;
+    static constexpr int RS = NT / KW;
+    static constexpr bool FP = (N == 64 || N == 128);
+    static constexpr int SW = FP ? N / RS : 1;     // spectrum sweeps per plane
+    static constexpr int XW = FP ? NP / RS : 1;    // split sweeps per plane
 };
 
 // next plane index >= q (stride gridDim.x) of an active right-hand side
@@ -536,6 +545,45 @@ __device__ __forceinline__ void plane_forward_core(cpx<T> *sh, const cpx<T> *tw,
                                                    int kz, int tid) {
     using C = PlaneCfg<N>;
     fft_lines<T, N, C::NP, C::NT, false>(sh, tw, C::NP, tid);
+    if constexpr (C::FP) {
+        const int kxl = tid % C::KW, ppl = tid / C::KW;
+        const int rd = ppl * C::LS + fft_pad(kxl), rdm = ppl * C::LS + fft_pad(kxl == 0 ? 0 : N - kxl);
+        cpx<T> ra[C::XW + 1], rb[C::XW + 1];
+#pragma unroll
+        for (int m = 0; m < C::XW; ++m) {
+            const cpx<T> Zk = sh[rd + m * C::RS * C::LS], Zm = sh[rdm + m * C::RS * C::LS];
+            ra[m] = {(T)0.5 * (Zk.x + Zm.x), (T)0.5 * (Zk.y - Zm.y)};
+            rb[m] = {(T)0.5 * (Zk.y + Zm.y), (T)-0.5 * (Zk.x - Zm.x)};
+        }
+        if (tid < C::NP) {                 // Nyquist column kx = KW of row pair tid
+            const cpx<T> Zk = sh[tid * C::LS + fft_pad(C::KW)];
+            ra[C::XW] = {(T)0.5 * (Zk.x + Zk.x), (T)0.5 * (Zk.y - Zk.y)};
+            rb[C::XW] = {(T)0.5 * (Zk.y + Zk.y), (T)-0.5 * (Zk.x - Zk.x)};
+        }
+        __syncthreads();
+        const int wr = kxl * C::LS + fft_pad(2 * ppl), wr1 = kxl * C::LS + fft_pad(2 * ppl + 1);
+#pragma unroll
+        for (int m = 0; m < C::XW; ++m) {
+            constexpr int step = 2 * C::RS + (2 * C::RS) / 16;
+            sh[wr + m * step] = ra[m];
+            sh[wr1 + m * step] = rb[m];
+        }
+        if (tid < C::NP) {
+            sh[C::KW * C::LS + fft_pad(2 * tid)] = ra[C::XW];
+            sh[C::KW * C::LS + fft_pad(2 * tid + 1)] = rb[C::XW];
+        }
+        __syncthreads();
+        fft_lines<T, N, C::NH, C::NT, false>(sh, tw, C::NH, tid);
+        // spectrum rows ky = kyl + RS m of columns kxl, and the Nyquist column
+        const int kyl = ppl;
+        cpx<T> *so = sr + ((int64_t)kyl * A.n2 + kz) * C::NH + kxl;
+        const int64_t sstep = (int64_t)C::RS * A.n2 * C::NH;
+        const int ld = kxl * C::LS + fft_pad(kyl);
+#pragma unroll
+        for (int m = 0; m < C::SW; ++m) so[m * sstep] = sh[ld + m * (C::RS + C::RS / 16)];
+        if (tid < N) sr[((int64_t)tid * A.n2 + kz) * C::NH + C::KW] = sh[C::KW * C::LS + fft_pad(tid)];
+        return;
+    }
     constexpr int NOUT = C::NP * C::NH;
     constexpr int MO = (NOUT + C::NT - 1) / C::NT;
     cpx<T> ra[MO], rb[MO];
@@ -642,6 +690,29 @@ template <typename T, int N>
 __device__ __forceinline__ void plane_inverse_core(cpx<T> *sh, const cpx<T> *tw, int tid) {
     using C = PlaneCfg<N>;
     fft_lines<T, N, C::NH, C::NT, true>(sh, tw, C::NH, tid);
+    if constexpr (C::FP) {
+        // output (row pair ppl + RP i, x = k) for thread (k, ppl) = (tid % N, tid / N)
+        constexpr int RP = C::NT / N, NI = C::NP / RP;
+        const int k = tid % N, ppl = tid / N;
+        const bool lo = k < C::NH;
+        const int kk = lo ? k : N - k;
+        const int ra0 = kk * C::LS + fft_pad(2 * ppl), rb0 = kk * C::LS + fft_pad(2 * ppl + 1);
+        constexpr int rstep = 2 * RP + (2 * RP) / 16;
+        cpx<T> rz[NI];
+#pragma unroll
+        for (int i = 0; i < NI; ++i) {
+            cpx<T> Av = sh[ra0 + i * rstep], Bv = sh[rb0 + i * rstep];
+            if (!lo) { Av.y = -Av.y; Bv.y = -Bv.y; }
+            rz[i] = {Av.x - Bv.y, Av.y + Bv.x};
+        }
+        __syncthreads();
+        const int w0 = ppl * C::LS + fft_pad(k);
+#pragma unroll
+        for (int i = 0; i < NI; ++i) sh[w0 + i * RP * C::LS] = rz[i];
+        __syncthreads();
+        fft_lines<T, N, C::NP, C::NT, true>(sh, tw, C::NP, tid);
+        return;
+    }
     constexpr int NOUT = C::NP * N;
     constexpr int MO = (NOUT + C::NT - 1) / C::NT;
     cpx<T> rz[MO];
@@ -684,6 +755,15 @@ __global__ __launch_bounds__(1024) void k_fft_plane_inv(FftArgs A, const cpx<T> 
         const int r = q / per_r, plane = q - r * per_r;
         const int c = plane / A.n2, kz = plane - c * A.n2;
         const cpx<T> *sr = spec + (int64_t)r * 3 * A.specN + (int64_t)c * A.specN;
+        if constexpr (C::FP) {
+            const int kxl = tid % C::KW, kyl = tid / C::KW;
+            const cpx<T> *si = sr + ((int64_t)kyl * A.n2 + kz) * C::NH + kxl;
+            const int64_t sstep = (int64_t)C::RS * A.n2 * C::NH;
+#pragma unroll
+            for (int m = 0; m < C::SW; ++m) sp[m] = si[m * sstep];
+            if (tid < N) sp[C::SW] = sr[((int64_t)tid * A.n2 + kz) * C::NH + C::KW];
+            return;
+        }
 #pragma unroll
         for (int i = 0; i < C::PS; ++i) {
             const int idx = tid + i * C::NT;
@@ -701,12 +781,20 @@ __global__ __launch_bounds__(1024) void k_fft_plane_inv(FftArgs A, const cpx<T> 
         // in registers across the whole loop
         asm volatile("" : "+v"(tid));
         const int r = q / per_r, plane = q - r * per_r;
+        if constexpr (C::FP) {
+            const int kxl = tid % C::KW, kyl = tid / C::KW;
+            const int st = kxl * C::LS + fft_pad(kyl);
 #pragma unroll
-        for (int i = 0; i < C::PS; ++i) {
-            const int idx = tid + i * C::NT;
-            if (C::NSP % C::NT == 0 || idx < C::NSP) {
-                const int ky = idx / C::NH, kx = idx - ky * C::NH;
-                sh[kx * C::LS + fft_pad(ky)] = sp[i];
+            for (int m = 0; m < C::SW; ++m) sh[st + m * (C::RS + C::RS / 16)] = sp[m];
+            if (tid < N) sh[C::KW * C::LS + fft_pad(tid)] = sp[C::SW];
+        } else {
+#pragma unroll
+            for (int i = 0; i < C::PS; ++i) {
+                const int idx = tid + i * C::NT;
+                if (C::NSP % C::NT == 0 || idx < C::NSP) {
+                    const int ky = idx / C::NH, kx = idx - ky * C::NH;
+                    sh[kx * C::LS + fft_pad(ky)] = sp[i];
+                }
             }
         }
         const int64_t base = (int64_t)r * 3 * A.N + (int64_t)plane * N * N;
@@ -721,7 +809,7 @@ __global__ __launch_bounds__(1024) void k_fft_plane_inv(FftArgs A, const cpx<T> 
                     const int idx = tid + i * C::NT;
                     if (C::NIN % C::NT == 0 || idx < C::NIN) {
                         const int pp = idx / N, x = idx - pp * N;
-                        const int64_t o0 = base + (2 * pp) * N + x;
+                        const int64_t o0 = base + (unsigned)((2 * pp) * N + x);
                         da[i] = d[o0]; db[i] = d[o0 + N];
                         ua[i] = u[o0]; ub[i] = u[o0 + N];
                     }
@@ -740,7 +828,7 @@ __global__ __launch_bounds__(1024) void k_fft_plane_inv(FftArgs A, const cpx<T> 
             if (C::NIN % C::NT == 0 || idx < C::NIN) {
                 const int pp = idx / N, x = idx - pp * N;
                 const cpx<T> yv = sh[pp * C::LS + fft_pad(x)];
-                const int64_t o0 = base + (2 * pp) * N + x, o1 = o0 + N;
+                const int64_t o0 = base + (unsigned)((2 * pp) * N + x), o1 = o0 + N;
                 if (mode == 0) {
                     out[o0] = yv.x;
                     out[o1] = yv.y;
