@@ -230,12 +230,12 @@ int autotune_depth(xfft_problem *p, Work<T> &w, const Tables<T> &tb, int nrhs) {
     HIP_OK(hipEventCreate(&e1));
     int best = p->slots.kz;
     float best_ms = 1e30f;
-    for (int kz : {4, 8, 16}) {
+    for (int kz : {4, 8, 16, 32}) {
         if (kz > p->g.n2) continue;
         set_depth(p->slots, p->g, kz);
         launch_operator<T>(p, w, tb, w.d, w.de, w.z, w.ze, false, (T)1, nrhs, nullptr, 0, nullptr, s, false);
         (void)hipEventRecord(e0, s);
-        for (int rep = 0; rep < 5; ++rep)
+        for (int rep = 0; rep < 10; ++rep)
             launch_operator<T>(p, w, tb, w.d, w.de, w.z, w.ze, false, (T)1, nrhs, nullptr, 0, nullptr, s, false);
         (void)hipEventRecord(e1, s);
         float ms = 0.0f;
@@ -589,7 +589,7 @@ void xfft_default_options(xfft_options *opt) {
     opt->precision = XFFT_FP64;
     opt->snap_eps = 1e-6;
     opt->d0_scale = 1.0;
-    opt->inner_rtol = 1e-4;
+    opt->inner_rtol = 1e-6;
     opt->batch = 1;
     opt->device = 0;
     opt->check_every = 8;

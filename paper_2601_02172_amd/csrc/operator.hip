@@ -296,14 +296,14 @@ __global__ __launch_bounds__(256) void k_regular(OpArgs<T> A) {
                 top[i] = F[4][i] + FB[9 + i][tid - 1] + FB[12 + i][tid - 16] + FB[15 + i][tid - 17];
             }
             if (kl >= k0) {
-                double dot = 0.0;
+                T dot = 0;                 // three terms in T, summed over the column in FP64
 #pragma unroll
                 for (int i = 0; i < 3; ++i) {
                     const T out = A.sign * (acc[i] + bot[i]);
                     y[i * N + vox] = out;
-                    if constexpr (HX) dot += (double)out * (double)Dp[sb][tx + TC * ty][i];
+                    if constexpr (HX) dot += out * Dp[sb][tx + TC * ty][i];
                 }
-                acc7[0] += dot;
+                acc7[0] += (double)dot;
             }
 #pragma unroll
             for (int i = 0; i < 3; ++i) acc[i] = top[i];

@@ -138,7 +138,7 @@ class Problem:
     """One periodic cell: grid, nodal level set, nodal phase labels, Lame pairs."""
 
     def __init__(self, n, length, levelset, phase, lame, *, rtol=1e-10, maxit=20000, precision="fp64",
-                 snap_eps=1e-6, d0_scale=1.0, inner_rtol=1e-4, batch=True, device=0, check_every=8,
+                 snap_eps=1e-6, d0_scale=1.0, inner_rtol=1e-6, batch=True, device=0, check_every=8,
                  use_graph=True, autotune=True, stream=None):
         lib = _lib()
         self._h = None
