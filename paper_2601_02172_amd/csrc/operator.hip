@@ -206,50 +206,53 @@ __global__ __launch_bounds__(256) void k_regular(OpArgs<T> A) {
     double acc7[7] = {0, 0, 0, 0, 0, 0, 0};
     double *vs = A.vstress ? A.vstress + (int64_t)r * 6 * N : nullptr;
 
-    // plane loads go through registers so that the next plane is in flight
-    // while the current layer is computed
-    T pre[2][3];
-    auto fetch_plane = [&](int kk) {
+    // plane loads go through registers two planes ahead of their use, so that
+    // the loads of plane kl + 3 are in flight while layer kl is computed and
+    // plane kl + 2 (loaded one layer earlier) is stored to LDS
+    T pre[2][3], pfar[2][3];
+    auto fetch_plane = [&](int kk, T (&dst)[2][3]) {
         if constexpr (HX) {
             const int64_t off = plane_sz * wrapi(kk, n2);
 #pragma unroll
             for (int u = 0; u < 2; ++u) {
                 if (tid + 256 * u < TC * TC) {
                     const int64_t node = colxy[u] + off;
-                    pre[u][0] = x[node];
-                    pre[u][1] = x[N + node];
-                    pre[u][2] = x[2 * N + node];
+                    dst[u][0] = x[node];
+                    dst[u][1] = x[N + node];
+                    dst[u][2] = x[2 * N + node];
                 }
             }
         }
     };
-    auto store_plane = [&](int slot) {
+    auto store_plane = [&](int slot, const T (&src)[2][3]) {
         if constexpr (HX) {
 #pragma unroll
             for (int u = 0; u < 2; ++u) {
                 const int col = tid + 256 * u;
                 if (col < TC * TC) {
-                    Dp[slot][col][0] = pre[u][0];
-                    Dp[slot][col][1] = pre[u][1];
-                    Dp[slot][col][2] = pre[u][2];
+                    Dp[slot][col][0] = src[u][0];
+                    Dp[slot][col][1] = src[u][1];
+                    Dp[slot][col][2] = src[u][2];
                 }
             }
         }
     };
 
-    fetch_plane(k0 - 1);
-    store_plane(0);
-    fetch_plane(k0);
-    store_plane(1);
+    fetch_plane(k0 - 1, pre);
+    store_plane(0, pre);
+    fetch_plane(k0, pre);
+    store_plane(1, pre);
+    if (k0 + 1 <= k1) fetch_plane(k0 + 1, pre);
     int m = A.vmat[colv + plane_sz * wrapi(k0 - 1, n2)];
+    int m_next = (k0 < k1) ? A.vmat[colv + plane_sz * wrapi(k0, n2)] : 0;
     __syncthreads();
 
     T acc[3] = {0, 0, 0};
     for (int s = 0, kl = k0 - 1; kl < k1; ++s, ++kl) {
         const int sb = s % 3, st = (s + 1) % 3;
-        const bool more = kl + 2 <= k1;
-        if (more) fetch_plane(kl + 2);
-        const int m_next = (kl + 1 < k1) ? A.vmat[colv + plane_sz * wrapi(kl + 1, n2)] : 0;
+        const bool more = kl + 2 <= k1, more2 = kl + 3 <= k1;
+        if (more2) fetch_plane(kl + 3, pfar);
+        const int m_far = (kl + 2 < k1) ? A.vmat[colv + plane_sz * wrapi(kl + 2, n2)] : 0;
         const int64_t vox = colv + plane_sz * wrapi(kl, n2);
         T F[8][3];
         if (m >= 0) {
@@ -286,7 +289,7 @@ __global__ __launch_bounds__(256) void k_regular(OpArgs<T> A) {
             FB[12 + i][tid] = F[6][i];
             FB[15 + i][tid] = F[7][i];
         }
-        if (more) store_plane((s + 2) % 3);
+        if (more) store_plane((s + 2) % 3, pre);
         __syncthreads();
         if (owner) {
             T bot[3], top[3];
@@ -309,6 +312,13 @@ __global__ __launch_bounds__(256) void k_regular(OpArgs<T> A) {
             for (int i = 0; i < 3; ++i) acc[i] = top[i];
         }
         m = m_next;
+        m_next = m_far;
+        if (more2) {
+#pragma unroll
+            for (int u = 0; u < 2; ++u)
+#pragma unroll
+                for (int i = 0; i < 3; ++i) pre[u][i] = pfar[u][i];
+        }
         __syncthreads();
     }
     block_sum<7>(acc7, red);
