@@ -110,10 +110,9 @@ template <typename T> struct Tables {
     T *lame = nullptr;       // [nphase][2]
     T *d0is = nullptr;       // [nX] D0^-1/2
     T *irr_L = nullptr;      // [nirr][8] snapped corner level set of irregular voxels
-    // [120][nirr] side moments of the Kuhn tets of irregular voxels, computed in
-    // FP64 and rounded once: row 20 t + k, k < 10 the + side and k >= 10 the -
-    // side, each the upper triangle of the symmetric 4 x 4 matrix row by row
-    // (rows of uncut tets hold zeros)
+    // [nirr][6][12] moments of the smaller side of each cut Kuhn tet of the
+    // irregular voxels (upper triangle; the sign bit of entry 0 marks the - side),
+    // computed in FP64 and rounded once
     T *irr_M = nullptr;
     cpx<T> *tw[3] = {nullptr, nullptr, nullptr};   // twiddles exp(-2 pi i t / n_axis)
     cpx<T> *tws[3] = {nullptr, nullptr, nullptr};  // stage-major twiddles of the compile-time LDS FFT

@@ -140,9 +140,12 @@ __device__ __forceinline__ int nth_bit(unsigned m, int k) {
     return __ffs(m) - 1;
 }
 
-// Second moments of both sides of a cut element (L has both signs).
+// Second moments Ms of the side of a cut element (L has both signs) that the
+// subdivision builds directly (one corner tetrahedron, or the prism side);
+// returns true when that is the + side.  The other side is the complement
+// M^tet - Ms.
 template <typename T>
-__device__ void side_moments(const T (&L)[4], T V, T (&Mp)[4][4], T (&Mm)[4][4]) {
+__device__ bool small_side_moments(const T (&L)[4], T V, T (&Ms)[4][4]) {
     unsigned pm = 0, nm = 0, zm = 0;
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
@@ -151,7 +154,6 @@ __device__ void side_moments(const T (&L)[4], T V, T (&Mp)[4][4], T (&Mm)[4][4])
         zm |= (L[a] == (T)0) ? (1u << a) : 0u;
     }
     const int np = __popc(pm), nn = __popc(nm), nz = __popc(zm);
-    T Ms[4][4];
 #pragma unroll
     for (int c = 0; c < 4; ++c)
 #pragma unroll
@@ -214,6 +216,13 @@ __device__ void side_moments(const T (&L)[4], T V, T (&Mp)[4][4], T (&Mm)[4][4])
         add_piece(Ms, B, V);
         small_is_pos = true;
     }
+    return small_is_pos;
+}
+
+// moments of both sides from the directly built side (entry of M^tet: V (1 + delta_cd) / 20)
+template <typename T>
+__device__ __forceinline__ void complete_sides(const T (&Ms)[4][4], bool small_is_pos, T V, T (&Mp)[4][4],
+                                               T (&Mm)[4][4]) {
     const T Vt = V * (T)0.05;
 #pragma unroll
     for (int c = 0; c < 4; ++c)
@@ -223,6 +232,14 @@ __device__ void side_moments(const T (&L)[4], T V, T (&Mp)[4][4], T (&Mm)[4][4])
             Mp[c][d] = small_is_pos ? Ms[c][d] : tot - Ms[c][d];
             Mm[c][d] = small_is_pos ? tot - Ms[c][d] : Ms[c][d];
         }
+}
+
+// Second moments of both sides of a cut element (L has both signs).
+template <typename T>
+__device__ void side_moments(const T (&L)[4], T V, T (&Mp)[4][4], T (&Mm)[4][4]) {
+    T Ms[4][4];
+    const bool pos = small_side_moments<T>(L, V, Ms);
+    complete_sides<T>(Ms, pos, V, Mp, Mm);
 }
 
 // barycentric gradient of vertex a of Kuhn tet t as a vector (compile-time t)

@@ -35,7 +35,7 @@ struct OpArgs {
     const int32_t *vmat, *irr, *irr_j, *irr_lab, *jlist, *enr_src;
     const T *d0is, *lame;
     const T *irr_L;           // [nirr][8] corner level set
-    const T *irr_M;           // [120][nirr] precomputed side moments
+    const T *irr_M;           // [nirr][6][12] precomputed moments of the directly built side
     T *cutbuf;
     double *partial;
     int nslots, slot0;
@@ -358,19 +358,36 @@ __device__ __forceinline__ void irregular_tet(const T (&Lc)[8], const T *__restr
         sym_axpy(S, (T)1, s);
         return;
     }
-    // Side moments, precomputed in FP64 at setup (the smaller side of a nearly
-    // degenerate split is a difference of O(1) moments and would lose all
-    // digits in FP32) and rounded once to T.
+    // Side moments: the smaller side was computed in FP64 at setup and rounded
+    // once (as a difference of O(1) moments it would lose all digits in FP32);
+    // the larger side is its complement.
     T Mp[4][4], Mm[4][4];
     {
+        T ms[12];
+        if constexpr (sizeof(T) == 4) {
+            const float4 *m4 = reinterpret_cast<const float4 *>(Mq + 12 * t);
+#pragma unroll
+            for (int e = 0; e < 3; ++e) {
+                const float4 w = m4[e];
+                ms[4 * e] = w.x; ms[4 * e + 1] = w.y; ms[4 * e + 2] = w.z; ms[4 * e + 3] = w.w;
+            }
+        } else {
+            const double2 *m2 = reinterpret_cast<const double2 *>(Mq + 12 * t);
+#pragma unroll
+            for (int e = 0; e < 5; ++e) {
+                const double2 w = m2[e];
+                ms[2 * e] = w.x; ms[2 * e + 1] = w.y;
+            }
+        }
+        const bool pos = !signbit(ms[0]);
+        ms[0] = fabs(ms[0]);
+        T Ms[4][4];
         int k = 0;
 #pragma unroll
         for (int c = 0; c < 4; ++c)
 #pragma unroll
-            for (int d = c; d < 4; ++d, ++k) {
-                Mp[c][d] = Mp[d][c] = Mq[(int64_t)(20 * t + k) * nirr];
-                Mm[c][d] = Mm[d][c] = Mq[(int64_t)(20 * t + 10 + k) * nirr];
-            }
+            for (int d = c; d < 4; ++d, ++k) Ms[c][d] = Ms[d][c] = ms[k];
+        complete_sides<T>(Ms, pos, V, Mp, Mm);
     }
     const Grad<T> Hq = kuhn_grad<t>(q);
 #pragma unroll
@@ -463,12 +480,12 @@ __global__ __launch_bounds__(128) void k_irregular(OpArgs<T> A) {
 #pragma unroll
             for (int d = 0; d < 3; ++d) F[c][d] = Fe[c][d] = (T)0;
         Sym<T> S = sym_zero<T>();
-        irregular_tet<0, T, EB>(Lc, A.irr_M + qv, A.nirr, U, Q, lab, A.lame, eb, F, Fe, S);
-        irregular_tet<1, T, EB>(Lc, A.irr_M + qv, A.nirr, U, Q, lab, A.lame, eb, F, Fe, S);
-        irregular_tet<2, T, EB>(Lc, A.irr_M + qv, A.nirr, U, Q, lab, A.lame, eb, F, Fe, S);
-        irregular_tet<3, T, EB>(Lc, A.irr_M + qv, A.nirr, U, Q, lab, A.lame, eb, F, Fe, S);
-        irregular_tet<4, T, EB>(Lc, A.irr_M + qv, A.nirr, U, Q, lab, A.lame, eb, F, Fe, S);
-        irregular_tet<5, T, EB>(Lc, A.irr_M + qv, A.nirr, U, Q, lab, A.lame, eb, F, Fe, S);
+        irregular_tet<0, T, EB>(Lc, A.irr_M + qv * 72, A.nirr, U, Q, lab, A.lame, eb, F, Fe, S);
+        irregular_tet<1, T, EB>(Lc, A.irr_M + qv * 72, A.nirr, U, Q, lab, A.lame, eb, F, Fe, S);
+        irregular_tet<2, T, EB>(Lc, A.irr_M + qv * 72, A.nirr, U, Q, lab, A.lame, eb, F, Fe, S);
+        irregular_tet<3, T, EB>(Lc, A.irr_M + qv * 72, A.nirr, U, Q, lab, A.lame, eb, F, Fe, S);
+        irregular_tet<4, T, EB>(Lc, A.irr_M + qv * 72, A.nirr, U, Q, lab, A.lame, eb, F, Fe, S);
+        irregular_tet<5, T, EB>(Lc, A.irr_M + qv * 72, A.nirr, U, Q, lab, A.lame, eb, F, Fe, S);
         // per-load buffer: FE corner forces [nirr][8][3], then scaled enriched ones [nirr][8][3]
         T *cb = A.cutbuf + (int64_t)r * A.nirr * 48 + qv * 24;
         T *cbe = cb + A.nirr * 24;

@@ -206,9 +206,14 @@ __global__ void k_irr_tables(int64_t nirr, int n0, int n1, int n2, const int32_t
     irr_labels_tet<5>(Lc, pc, lab);
 }
 
-// Side moments of the six Kuhn tets of every irregular voxel (eq. of the exact
+// Side moments of the six Kuhn tets of every irregular voxel (exact
 // integration over the two sides of a cut element): geometry only, so they are
-// computed once per setup instead of in every operator application.
+// computed once per setup in FP64 instead of in every operator application.
+// Stored per voxel and tet, 12 values [qv][t][12]: the upper triangle (row by
+// row) of the moments of the side with the smaller volume, whose entry 0
+// carries the sign bit when that side is the - side (all moments are >= 0),
+// then two zeros.  The operator forms the other side as the complement
+// M^tet - Ms, which is accurate in FP32 because it is the larger side.
 __global__ void k_irr_moments(int64_t nirr, const double *irr_L64, double *M64, float *M32) {
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= nirr) return;
@@ -224,26 +229,45 @@ __global__ void k_irr_moments(int64_t nirr, const double *irr_L64, double *M64, 
             anyp |= L[a] > 0.0;
             anyn |= L[a] < 0.0;
         }
-        double Mp[4][4], Mm[4][4];
+        double Ms[4][4];
+        bool pos = true;
         if (anyp && anyn) {
-            side_moments<double>(L, 1.0 / 6.0, Mp, Mm);
+            pos = small_side_moments<double>(L, 1.0 / 6.0, Ms);
+            // keep the side of smaller volume (sum of the moments): its
+            // complement is then the larger side and is formed accurately in FP32
+            const double Vt = (1.0 / 6.0) * 0.05;
+            double vs = 0.0;
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+#pragma unroll
+                for (int d = 0; d < 4; ++d) vs += Ms[c][d];
+            if (vs > 0.5 * (20.0 * Vt)) {      // the whole tet: sum of V (1 + delta_cd) / 20 = V
+#pragma unroll
+                for (int c = 0; c < 4; ++c)
+#pragma unroll
+                    for (int d = 0; d < 4; ++d) Ms[c][d] = Vt * (c == d ? 2.0 : 1.0) - Ms[c][d];
+                pos = !pos;
+            }
         } else {
 #pragma unroll
             for (int c = 0; c < 4; ++c)
 #pragma unroll
-                for (int d = 0; d < 4; ++d) Mp[c][d] = Mm[c][d] = 0.0;
+                for (int d = 0; d < 4; ++d) Ms[c][d] = 0.0;
         }
+        double v[12];
         int k = 0;
 #pragma unroll
         for (int c = 0; c < 4; ++c)
 #pragma unroll
-            for (int d = c; d < 4; ++d, ++k) {
-                const int64_t op = (int64_t)(20 * t + k) * nirr + q, om = (int64_t)(20 * t + 10 + k) * nirr + q;
-                M64[op] = Mp[c][d];
-                M64[om] = Mm[c][d];
-                M32[op] = (float)Mp[c][d];
-                M32[om] = (float)Mm[c][d];
-            }
+            for (int d = c; d < 4; ++d, ++k) v[k] = Ms[c][d];
+        v[10] = v[11] = 0.0;
+        if (!pos) v[0] = -v[0];                       // sign bit marks the - side (also for +0)
+        const int64_t o = (q * 6 + t) * 12;
+#pragma unroll
+        for (int e = 0; e < 12; ++e) {
+            M64[o + e] = v[e];
+            M32[o + e] = (float)v[e];
+        }
     }
 }
 
@@ -461,8 +485,8 @@ int run_setup(xfft_problem *p, const double *L_dev_raw) {
             hipMalloc(&p->irr_lab, sizeof(int32_t) * 12 * nirr) != hipSuccess ||
             hipMalloc(&p->t64.irr_L, sizeof(double) * 8 * nirr) != hipSuccess ||
             hipMalloc(&p->t32.irr_L, sizeof(float) * 8 * nirr) != hipSuccess ||
-            hipMalloc(&p->t64.irr_M, sizeof(double) * 120 * nirr) != hipSuccess ||
-            hipMalloc(&p->t32.irr_M, sizeof(float) * 120 * nirr) != hipSuccess ||
+            hipMalloc(&p->t64.irr_M, sizeof(double) * 72 * nirr) != hipSuccess ||
+            hipMalloc(&p->t32.irr_M, sizeof(float) * 72 * nirr) != hipSuccess ||
             hipMalloc(&p->d0, sizeof(double) * nX) != hipSuccess ||
             hipMalloc(&p->t64.d0is, sizeof(double) * nX) != hipSuccess ||
             hipMalloc(&p->t32.d0is, sizeof(float) * nX) != hipSuccess ||
