@@ -192,6 +192,63 @@ def cpu_baseline(cfg, fp64_iters, sample_cut=2000, sample_iters=2):
                 seconds_setup_est=t_setup, seconds_per_iteration=t_iter)
 
 
+def bench_uneven(args):
+    """Sixteen RVEs of uneven size (32..128)^3, six loads each: 96 solves as one
+    captured graph (mixed precision), against the same problems solved one
+    after the other, and C_eff against FP64 solves at rtol 1e-13."""
+    import torch
+    import microstructure as ms
+    from paper_2601_02172_amd import Problem, batch_effective_stiffness
+    t0 = time.perf_counter()
+    cfgs = ms.config_uneven_batch()
+    log(f"16 RVEs generated in {time.perf_counter() - t0:.1f}s: n = {[c['n'][0] for c in cfgs]}")
+    probs = [Problem(c["n"], c["length"], c["L"], c["phase"], c["lame"], rtol=args.rtol, precision="mixed",
+                     inner_rtol=args.inner_rtol) for c in cfgs]
+    try:
+        for _ in range(args.warmup):
+            batch_effective_stiffness(probs)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            Cb, st = batch_effective_stiffness(probs, with_stats=True)
+        torch.cuda.synchronize()
+        t_batch = (time.perf_counter() - t0) / args.steps
+        # the same problems one after the other (each with its six loads batched)
+        for p in probs:
+            p.effective_stiffness()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            for p in probs:
+                p.effective_stiffness()
+        torch.cuda.synchronize()
+        t_seq = (time.perf_counter() - t0) / args.steps
+    finally:
+        for p in probs:
+            p.close()
+    errs = []
+    for i, c in enumerate(cfgs):
+        with Problem(c["n"], c["length"], c["L"], c["phase"], c["lame"], rtol=1e-13) as pr:
+            C_ref = pr.effective_stiffness()[0]
+        errs.append(float(np.linalg.norm(Cb[i] - C_ref) / np.linalg.norm(C_ref)))
+    nsolve = 6 * len(cfgs)
+    log(f"batch: {1000 * t_batch:.1f} ms for {nsolve} solves; one RVE after the other: {1000 * t_seq:.1f} ms; "
+        f"max C_eff rel error {max(errs):.2e}")
+    out = {
+        "metric": "PCG solves/sec, 16 uneven RVEs x 6 loads as one batch (mixed)",
+        "value": round(nsolve / t_batch, 4), "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(1000 * t_batch, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32 (FP64 refinement)", "data": "synthetic",
+        "config": {"workload": "uneven16: 16 RVEs n in {32,48,64,96,128}, spheres vf 0.1-0.3 (achieved "
+                   f"{min(c['info']['vf'] for c in cfgs):.2f}-{max(c['info']['vf'] for c in cfgs):.2f}), contrast 100",
+                   "rtol": args.rtol, "inner_rtol": args.inner_rtol, "voxels": int(sum(np.prod(c["n"]) for c in cfgs))},
+        "roofline": None, "cpu_baseline": None,
+        "sequential_solves_per_s": round(nsolve / t_seq, 4),
+        "c_eff_rel_error_max": max(errs), "iters": np.asarray(st["iters"]).tolist(),
+    }
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -201,7 +258,7 @@ def main():
     ap.add_argument("--inner-rtol", type=float, default=1e-6)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
-    ap.add_argument("--workload", default="spheres128", choices=["spheres128", "ellipsoids256"])
+    ap.add_argument("--workload", default="spheres128", choices=["spheres128", "ellipsoids256", "uneven16"])
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="summarise two rocprofv3 --pmc runs of this script (FETCH_SIZE, WRITE_SIZE) as JSON")
     args = ap.parse_args()
@@ -218,6 +275,8 @@ def main():
     from paper_2601_02172_amd import Problem
 
     torch.cuda.init()
+    if args.workload == "uneven16":
+        return bench_uneven(args)
     t_gen = time.perf_counter()
     if args.workload == "spheres128":
         cfg = ms.config_spheres128()

@@ -30,13 +30,15 @@ def spheres_levelset(n, centers, radii):
     return best.astype(np.float64), phase
 
 
-def rsa_spheres(n, count, radius_sampler, gap, rng, max_tries=200000, target_vf=None):
+def rsa_spheres(n, count, radius_sampler, gap, rng, max_tries=200000, target_vf=None, allow_short=False):
     """Random sequential addition of non-overlapping periodic spheres.
 
     Centres are uniform in the cell; a candidate is accepted when its surface
     keeps at least ``gap`` voxels from every accepted sphere.  Stops after
     ``count`` spheres, or, when ``target_vf`` is given, once the analytic volume
-    fraction reaches it.
+    fraction reaches it.  With ``allow_short`` the spheres placed within
+    ``max_tries`` candidates are returned when the target is out of reach
+    (random sequential addition jams well below dense packing).
     """
     n = np.asarray(n, dtype=np.float64)
     vol = float(np.prod(n))
@@ -49,20 +51,19 @@ def rsa_spheres(n, count, radius_sampler, gap, rng, max_tries=200000, target_vf=
         if target_vf is not None and vf >= target_vf:
             break
         if tries >= max_tries:
+            if allow_short:
+                break
             raise RuntimeError("RSA did not place the requested inclusions")
         tries += 1
         r = float(radius_sampler(rng))
         c = rng.uniform(0.0, 1.0, 3) * n
-        ok = True
-        for c2, r2 in zip(centers, radii):
-            d = periodic_delta(c, np.asarray(c2), n)
-            if np.sqrt(np.sum(d * d)) < r + r2 + gap:
-                ok = False
-                break
-        if ok:
-            centers.append(c)
-            radii.append(r)
-            vf += 4.0 / 3.0 * np.pi * r ** 3 / vol
+        if centers:
+            d = periodic_delta(c[None, :], np.asarray(centers), n[None, :])
+            if np.any(np.sqrt(np.sum(d * d, axis=1)) < r + np.asarray(radii) + gap):
+                continue
+        centers.append(c)
+        radii.append(r)
+        vf += 4.0 / 3.0 * np.pi * r ** 3 / vol
     return np.array(centers), np.array(radii)
 
 
