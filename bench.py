@@ -71,7 +71,9 @@ def algorithmic_bytes(g, s, nrhs):
     field = 3 * N * s                            # one 3-component nodal field
     per = {
         "regular_voxels": 2 * field + 4 * N,                      # read d, write z, read material ids
-        "irregular_voxels": nirr * (8 * 3 * s + 8 * s + 8 * 4 + 12 * 4 + 8 * 3 * s + 48 * s),
+        # u, level set, enriched ids, labels, scaled enriched d, corner forces; moments per cut element
+        "irregular_voxels": nirr * (8 * 3 * s + 8 * s + 8 * 4 + 12 * 4 + 8 * 3 * s + 48 * s)
+                            + g.get("n_cut_elements", 0) * 12 * s,
         "enriched_gather": nX * (8 * 4 + 3 * s),
         "fft_x_forward": 3 * field + spec,                        # read f, z; write f, spectrum
         "fft_y_forward": 2 * spec,
