@@ -255,6 +255,15 @@ __global__ __launch_bounds__(256) void k_regular(OpArgs<T> A) {
         const int m_far = (kl + 2 < k1) ? A.vmat[colv + plane_sz * wrapi(kl + 2, n2)] : 0;
         const int64_t vox = colv + plane_sz * wrapi(kl, n2);
         T F[8][3];
+        if (m < 0) {
+            // buffered corner forces of an irregular voxel: the loads are issued
+            // before the regular lanes compute, so their latency is overlapped
+            const T *cb = cutbuf + (int64_t)(-m - 1) * 24;
+#pragma unroll
+            for (int c = 0; c < 8; ++c)
+#pragma unroll
+                for (int i = 0; i < 3; ++i) F[c][i] = cb[3 * c + i];
+        }
         if (m >= 0) {
             T U[8][3];
 #pragma unroll
@@ -272,12 +281,6 @@ __global__ __launch_bounds__(256) void k_regular(OpArgs<T> A) {
                 add_sym(acc7, S);
                 if (vs) store_vstress(vs, N, vox, S);
             }
-        } else {
-            const T *cb = cutbuf + (int64_t)(-m - 1) * 24;
-#pragma unroll
-            for (int c = 0; c < 8; ++c)
-#pragma unroll
-                for (int i = 0; i < 3; ++i) F[c][i] = cb[3 * c + i];
         }
         // publish the corners that belong to other threads' nodes
 #pragma unroll
