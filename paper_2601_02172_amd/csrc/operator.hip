@@ -158,6 +158,19 @@ __device__ __forceinline__ void regular_voxel(const T (&U)[8][3], const T (&eb)[
     }
 }
 
+// value of lane - 1 within each row of 16 lanes (DPP row_shr:1); lane 0 of a
+// row receives 0.  The tile's thread (tx, ty) is lane tx + 16 (ty % 4) of its
+// wave, so lane - 1 is the thread at tx - 1 for tx >= 1.
+__device__ __forceinline__ float dpp_row_shr1(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x111, 0xF, 0xF, true));
+}
+__device__ __forceinline__ double dpp_row_shr1(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), 0x111, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x111, 0xF, 0xF, true);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
 // z-marching tile kernel.  Block = 16 x 16 threads; thread (tx, ty) evaluates the
 // voxel column with base (i0 - 1 + tx, j0 - 1 + ty) and owns the node column
 // with the same base when tx, ty >= 1.  Node (a, b) collects corner c of the
@@ -166,7 +179,7 @@ __device__ __forceinline__ void regular_voxel(const T (&U)[8][3], const T (&eb)[
 template <typename T, bool HX, bool EB, bool ST>
 __global__ __launch_bounds__(256) void k_regular(OpArgs<T> A) {
     __shared__ T Dp[3][TC * TC][3];
-    __shared__ T FB[18][TE * TE];      // structure of arrays: lanes hit consecutive banks
+    __shared__ T FB[2][6][TE * TE];    // row sums for the node above, double-buffered by layer parity
     __shared__ double red[4 * 7];
 
     // logical block: (rhs, z chunk, tile y, tile x), x fastest
@@ -282,24 +295,33 @@ __global__ __launch_bounds__(256) void k_regular(OpArgs<T> A) {
                 if (vs) store_vstress(vs, N, vox, S);
             }
         }
-        // publish the corners that belong to other threads' nodes
+        // Corner sums of node (a, b): own corner 0 (4), corner 1 (5) of the voxel
+        // at a - 1 (lane tx - 1 of the same 16-lane row, moved by DPP), and the
+        // row sum "corner 2 (6) + left neighbour's corner 3 (7)" of the thread
+        // at b - 1, exchanged through LDS.
+        const int fb = s & 1;
+        T bot[3], top[3];
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
-            FB[0 + i][tid] = F[1][i];
-            FB[3 + i][tid] = F[2][i];
-            FB[6 + i][tid] = F[3][i];
-            FB[9 + i][tid] = F[5][i];
-            FB[12 + i][tid] = F[6][i];
-            FB[15 + i][tid] = F[7][i];
+            bot[i] = F[0][i] + dpp_row_shr1(F[1][i]);
+            top[i] = F[4][i] + dpp_row_shr1(F[5][i]);
+            FB[fb][i][tid] = F[2][i] + dpp_row_shr1(F[3][i]);
+            FB[fb][3 + i][tid] = F[6][i] + dpp_row_shr1(F[7][i]);
+        }
+        T dv[3] = {0, 0, 0};
+        if constexpr (HX) {
+#pragma unroll
+            for (int i = 0; i < 3; ++i) dv[i] = Dp[sb][tx + TC * ty][i];
         }
         if (more) store_plane((s + 2) % 3, pre);
+        // one barrier per layer: the row sums are double-buffered, the Dp slot
+        // written next layer was last read before this barrier
         __syncthreads();
         if (owner) {
-            T bot[3], top[3];
 #pragma unroll
             for (int i = 0; i < 3; ++i) {
-                bot[i] = F[0][i] + FB[0 + i][tid - 1] + FB[3 + i][tid - 16] + FB[6 + i][tid - 17];
-                top[i] = F[4][i] + FB[9 + i][tid - 1] + FB[12 + i][tid - 16] + FB[15 + i][tid - 17];
+                bot[i] += FB[fb][i][tid - 16];
+                top[i] += FB[fb][3 + i][tid - 16];
             }
             if (kl >= k0) {
                 T dot = 0;                 // three terms in T, summed over the column in FP64
@@ -307,7 +329,7 @@ __global__ __launch_bounds__(256) void k_regular(OpArgs<T> A) {
                 for (int i = 0; i < 3; ++i) {
                     const T out = A.sign * (acc[i] + bot[i]);
                     y[i * N + vox] = out;
-                    if constexpr (HX) dot += out * Dp[sb][tx + TC * ty][i];
+                    if constexpr (HX) dot += out * dv[i];
                 }
                 acc7[0] += (double)dot;
             }
@@ -322,8 +344,8 @@ __global__ __launch_bounds__(256) void k_regular(OpArgs<T> A) {
 #pragma unroll
                 for (int i = 0; i < 3; ++i) pre[u][i] = pfar[u][i];
         }
-        __syncthreads();
     }
+    __syncthreads();
     block_sum<7>(acc7, red);
     if (tid == 0) {
         double *P = A.partial + ((int64_t)r * A.nslots + A.slot0 + blk) * NPART;
