@@ -511,10 +511,14 @@ __global__ __launch_bounds__(256) void k_fft_y_t(FftArgs A, const cpx<T> *tw, cp
 // plane): the global loads of the next plane are issued into registers before
 // the current plane is transformed, so HBM traffic overlaps the LDS and ALU
 // work of the transform.  Without PIPE there is one workgroup per plane.
+// LDS uses the interleaved layout of fft_lines.h (line l at l * (N | 1), no
+// padding), so the transposes between the x and y transforms, which address
+// 32 consecutive lines at one offset or one line at 32 consecutive offsets,
+// are conflict free as well.
 template <int N> struct PlaneCfg {
     static constexpr int NH = N / 2 + 1;
     static constexpr int NP = N / 2;
-    static constexpr int LS = fft_ls(N);
+    static constexpr int LS = lds_ls<true>(N);
     static constexpr int NT = 1024;
     static constexpr int ELEMS = NH * LS;      // >= NP * LS
     static constexpr int NIN = NP * N;         // packed row-pair elements of a plane
@@ -544,10 +548,10 @@ template <typename T, int N>
 __device__ __forceinline__ void plane_forward_core(cpx<T> *sh, const cpx<T> *tw, const FftArgs &A, cpx<T> *sr,
                                                    int kz, int tid) {
     using C = PlaneCfg<N>;
-    fft_lines<T, N, C::NP, C::NT, false>(sh, tw, C::NP, tid);
+    fft_lines<T, N, C::NP, C::NT, false, true>(sh, tw, C::NP, tid);
     if constexpr (C::FP) {
         const int kxl = tid % C::KW, ppl = tid / C::KW;
-        const int rd = ppl * C::LS + fft_pad(kxl), rdm = ppl * C::LS + fft_pad(kxl == 0 ? 0 : N - kxl);
+        const int rd = ppl * C::LS + kxl, rdm = ppl * C::LS + (kxl == 0 ? 0 : N - kxl);
         cpx<T> ra[C::XW + 1], rb[C::XW + 1];
 #pragma unroll
         for (int m = 0; m < C::XW; ++m) {
@@ -556,32 +560,32 @@ __device__ __forceinline__ void plane_forward_core(cpx<T> *sh, const cpx<T> *tw,
             rb[m] = {(T)0.5 * (Zk.y + Zm.y), (T)-0.5 * (Zk.x - Zm.x)};
         }
         if (tid < C::NP) {                 // Nyquist column kx = KW of row pair tid
-            const cpx<T> Zk = sh[tid * C::LS + fft_pad(C::KW)];
+            const cpx<T> Zk = sh[tid * C::LS + C::KW];
             ra[C::XW] = {(T)0.5 * (Zk.x + Zk.x), (T)0.5 * (Zk.y - Zk.y)};
             rb[C::XW] = {(T)0.5 * (Zk.y + Zk.y), (T)-0.5 * (Zk.x - Zk.x)};
         }
         __syncthreads();
-        const int wr = kxl * C::LS + fft_pad(2 * ppl), wr1 = kxl * C::LS + fft_pad(2 * ppl + 1);
+        const int wr = kxl * C::LS + 2 * ppl, wr1 = kxl * C::LS + 2 * ppl + 1;
 #pragma unroll
         for (int m = 0; m < C::XW; ++m) {
-            constexpr int step = 2 * C::RS + (2 * C::RS) / 16;
+            constexpr int step = 2 * C::RS;
             sh[wr + m * step] = ra[m];
             sh[wr1 + m * step] = rb[m];
         }
         if (tid < C::NP) {
-            sh[C::KW * C::LS + fft_pad(2 * tid)] = ra[C::XW];
-            sh[C::KW * C::LS + fft_pad(2 * tid + 1)] = rb[C::XW];
+            sh[C::KW * C::LS + 2 * tid] = ra[C::XW];
+            sh[C::KW * C::LS + 2 * tid + 1] = rb[C::XW];
         }
         __syncthreads();
-        fft_lines<T, N, C::NH, C::NT, false>(sh, tw, C::NH, tid);
+        fft_lines<T, N, C::NH, C::NT, false, true>(sh, tw, C::NH, tid);
         // spectrum rows ky = kyl + RS m of columns kxl, and the Nyquist column
         const int kyl = ppl;
         cpx<T> *so = sr + ((int64_t)kyl * A.n2 + kz) * C::NH + kxl;
         const int64_t sstep = (int64_t)C::RS * A.n2 * C::NH;
-        const int ld = kxl * C::LS + fft_pad(kyl);
+        const int ld = kxl * C::LS + kyl;
 #pragma unroll
-        for (int m = 0; m < C::SW; ++m) so[m * sstep] = sh[ld + m * (C::RS + C::RS / 16)];
-        if (tid < N) sr[((int64_t)tid * A.n2 + kz) * C::NH + C::KW] = sh[C::KW * C::LS + fft_pad(tid)];
+        for (int m = 0; m < C::SW; ++m) so[m * sstep] = sh[ld + m * C::RS];
+        if (tid < N) sr[((int64_t)tid * A.n2 + kz) * C::NH + C::KW] = sh[C::KW * C::LS + tid];
         return;
     }
     constexpr int NOUT = C::NP * C::NH;
@@ -592,8 +596,8 @@ __device__ __forceinline__ void plane_forward_core(cpx<T> *sh, const cpx<T> *tw,
         const int idx = tid + i * C::NT;
         if (idx < NOUT) {
             const int pp = idx / C::NH, kx = idx - pp * C::NH;
-            const cpx<T> Zk = sh[pp * C::LS + fft_pad(kx)];
-            const cpx<T> Zm = sh[pp * C::LS + fft_pad(kx == 0 ? 0 : N - kx)];
+            const cpx<T> Zk = sh[pp * C::LS + kx];
+            const cpx<T> Zm = sh[pp * C::LS + (kx == 0 ? 0 : N - kx)];
             ra[i] = {(T)0.5 * (Zk.x + Zm.x), (T)0.5 * (Zk.y - Zm.y)};
             rb[i] = {(T)0.5 * (Zk.y + Zm.y), (T)-0.5 * (Zk.x - Zm.x)};
         }
@@ -604,15 +608,15 @@ __device__ __forceinline__ void plane_forward_core(cpx<T> *sh, const cpx<T> *tw,
         const int idx = tid + i * C::NT;
         if (idx < NOUT) {
             const int pp = idx / C::NH, kx = idx - pp * C::NH;
-            sh[kx * C::LS + fft_pad(2 * pp)] = ra[i];
-            sh[kx * C::LS + fft_pad(2 * pp + 1)] = rb[i];
+            sh[kx * C::LS + 2 * pp] = ra[i];
+            sh[kx * C::LS + 2 * pp + 1] = rb[i];
         }
     }
     __syncthreads();
-    fft_lines<T, N, C::NH, C::NT, false>(sh, tw, C::NH, tid);
+    fft_lines<T, N, C::NH, C::NT, false, true>(sh, tw, C::NH, tid);
     for (int idx = tid; idx < N * C::NH; idx += C::NT) {
         const int ky = idx / C::NH, kx = idx - ky * C::NH;
-        sr[((int64_t)ky * A.n2 + kz) * C::NH + kx] = sh[kx * C::LS + fft_pad(ky)];
+        sr[((int64_t)ky * A.n2 + kz) * C::NH + kx] = sh[kx * C::LS + ky];
     }
 }
 
@@ -666,7 +670,7 @@ __global__ __launch_bounds__(1024) void k_fft_plane_fwd(FftArgs A, const cpx<T> 
                     fr[o0] = a;
                     fr[o0 + N] = b;
                 }
-                sh[pp * C::LS + fft_pad(x)] = {a, b};
+                sh[pp * C::LS + x] = {a, b};
             }
         }
         if constexpr (!PIPE) {
@@ -689,15 +693,15 @@ __global__ __launch_bounds__(1024) void k_fft_plane_fwd(FftArgs A, const cpx<T> 
 template <typename T, int N>
 __device__ __forceinline__ void plane_inverse_core(cpx<T> *sh, const cpx<T> *tw, int tid) {
     using C = PlaneCfg<N>;
-    fft_lines<T, N, C::NH, C::NT, true>(sh, tw, C::NH, tid);
+    fft_lines<T, N, C::NH, C::NT, true, true>(sh, tw, C::NH, tid);
     if constexpr (C::FP) {
         // output (row pair ppl + RP i, x = k) for thread (k, ppl) = (tid % N, tid / N)
         constexpr int RP = C::NT / N, NI = C::NP / RP;
         const int k = tid % N, ppl = tid / N;
         const bool lo = k < C::NH;
         const int kk = lo ? k : N - k;
-        const int ra0 = kk * C::LS + fft_pad(2 * ppl), rb0 = kk * C::LS + fft_pad(2 * ppl + 1);
-        constexpr int rstep = 2 * RP + (2 * RP) / 16;
+        const int ra0 = kk * C::LS + 2 * ppl, rb0 = kk * C::LS + 2 * ppl + 1;
+        constexpr int rstep = 2 * RP;
         cpx<T> rz[NI];
 #pragma unroll
         for (int i = 0; i < NI; ++i) {
@@ -706,11 +710,11 @@ __device__ __forceinline__ void plane_inverse_core(cpx<T> *sh, const cpx<T> *tw,
             rz[i] = {Av.x - Bv.y, Av.y + Bv.x};
         }
         __syncthreads();
-        const int w0 = ppl * C::LS + fft_pad(k);
+        const int w0 = ppl * C::LS + k;
 #pragma unroll
         for (int i = 0; i < NI; ++i) sh[w0 + i * RP * C::LS] = rz[i];
         __syncthreads();
-        fft_lines<T, N, C::NP, C::NT, true>(sh, tw, C::NP, tid);
+        fft_lines<T, N, C::NP, C::NT, true, true>(sh, tw, C::NP, tid);
         return;
     }
     constexpr int NOUT = C::NP * N;
@@ -723,7 +727,7 @@ __device__ __forceinline__ void plane_inverse_core(cpx<T> *sh, const cpx<T> *tw,
             const int pp = idx / N, k = idx - pp * N;
             const bool lo = k < C::NH;
             const int kk = lo ? k : N - k;
-            cpx<T> Av = sh[kk * C::LS + fft_pad(2 * pp)], Bv = sh[kk * C::LS + fft_pad(2 * pp + 1)];
+            cpx<T> Av = sh[kk * C::LS + 2 * pp], Bv = sh[kk * C::LS + 2 * pp + 1];
             if (!lo) { Av.y = -Av.y; Bv.y = -Bv.y; }
             rz[i] = {Av.x - Bv.y, Av.y + Bv.x};
         }
@@ -734,11 +738,11 @@ __device__ __forceinline__ void plane_inverse_core(cpx<T> *sh, const cpx<T> *tw,
         const int idx = tid + i * C::NT;
         if (idx < NOUT) {
             const int pp = idx / N, k = idx - pp * N;
-            sh[pp * C::LS + fft_pad(k)] = rz[i];
+            sh[pp * C::LS + k] = rz[i];
         }
     }
     __syncthreads();
-    fft_lines<T, N, C::NP, C::NT, true>(sh, tw, C::NP, tid);
+    fft_lines<T, N, C::NP, C::NT, true, true>(sh, tw, C::NP, tid);
 }
 
 // mode 0: out = G f; mode 1: u += alpha d, d = G f + beta d; mode 2: d = G f
@@ -783,17 +787,17 @@ __global__ __launch_bounds__(1024) void k_fft_plane_inv(FftArgs A, const cpx<T> 
         const int r = q / per_r, plane = q - r * per_r;
         if constexpr (C::FP) {
             const int kxl = tid % C::KW, kyl = tid / C::KW;
-            const int st = kxl * C::LS + fft_pad(kyl);
+            const int st = kxl * C::LS + kyl;
 #pragma unroll
-            for (int m = 0; m < C::SW; ++m) sh[st + m * (C::RS + C::RS / 16)] = sp[m];
-            if (tid < N) sh[C::KW * C::LS + fft_pad(tid)] = sp[C::SW];
+            for (int m = 0; m < C::SW; ++m) sh[st + m * C::RS] = sp[m];
+            if (tid < N) sh[C::KW * C::LS + tid] = sp[C::SW];
         } else {
 #pragma unroll
             for (int i = 0; i < C::PS; ++i) {
                 const int idx = tid + i * C::NT;
                 if (C::NSP % C::NT == 0 || idx < C::NSP) {
                     const int ky = idx / C::NH, kx = idx - ky * C::NH;
-                    sh[kx * C::LS + fft_pad(ky)] = sp[i];
+                    sh[kx * C::LS + ky] = sp[i];
                 }
             }
         }
@@ -827,7 +831,7 @@ __global__ __launch_bounds__(1024) void k_fft_plane_inv(FftArgs A, const cpx<T> 
             const int idx = tid + i * C::NT;
             if (C::NIN % C::NT == 0 || idx < C::NIN) {
                 const int pp = idx / N, x = idx - pp * N;
-                const cpx<T> yv = sh[pp * C::LS + fft_pad(x)];
+                const cpx<T> yv = sh[pp * C::LS + x];
                 const int64_t o0 = base + (unsigned)((2 * pp) * N + x), o1 = o0 + N;
                 if (mode == 0) {
                     out[o0] = yv.x;
@@ -864,12 +868,16 @@ __global__ __launch_bounds__(1024) void k_fft_plane_inv(FftArgs A, const cpx<T> 
 // (neighbouring runs share cache lines).  Thread (kl, z0) = (tid % TK, tid / TK)
 // handles column kl at rows z0 + m ZR (ZR = 512 / TK): when ZR divides n2 all
 // global and LDS offsets of its elements are compile-time constants added to
-// three per-thread bases.
+// three per-thread bases.  With 3 TK >= 32 lines the LDS uses the interleaved
+// layout of fft_lines.h; the two row groups of a half wave then sit ZR / 2
+// rows apart, so that the 16 columns x 2 rows of a half wave fall on 32
+// different banks in the staging and Green phases too.
 template <typename T, int N2, int TK>
 __global__ __launch_bounds__(512) void k_fft_z_t(FftArgs A, const cpx<T> *tw, const T *h0, const T *h1,
                                                   const T *h2, cpx<T> *spec, int64_t sz, int64_t sy, int nrhs) {
-    constexpr int LS = fft_ls(N2);
     constexpr int NL = 3 * TK;
+    constexpr bool ILV = NL >= 32;
+    constexpr int LS = lds_ls<ILV>(N2);
     constexpr int NE = NL * N2;                     // staged elements of a workgroup
     static_assert(512 % TK == 0, "TK must divide the workgroup");
     constexpr int ZR = 512 / TK;
@@ -894,7 +902,8 @@ __global__ __launch_bounds__(512) void k_fft_z_t(FftArgs A, const cpx<T> *tw, co
     const int kx0 = tile * tk, ncol = min(tk, nh - kx0);
     cpx<T> *base = spec + (int64_t)r * 3 * A.specN + (int64_t)ky * sy + kx0;
     const int tid = threadIdx.x;
-    const int kl = tid % TK, z0 = tid / TK;
+    const int kl = tid % TK, q = tid / TK;
+    const int z0 = (ILV && TK == 16 && ZR % 2 == 0) ? (q >> 1) + (ZR / 2) * (q & 1) : q;
     const T scale = (T)(1.0 / ((double)A.n0 * (double)A.n1 * (double)N2));
     double part = 0.0;
     if constexpr (FAST) {
@@ -903,23 +912,23 @@ __global__ __launch_bounds__(512) void k_fft_z_t(FftArgs A, const cpx<T> *tw, co
         cpx<T> *gb = base + kl + (int64_t)z0 * sz;
         int lb[3];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) lb[c] = (c * tk + kl) * LS + fft_pad(z0);
+        for (int c = 0; c < 3; ++c) lb[c] = (c * tk + kl) * LS + lds_pos<ILV>(z0);
         if (kl < tk) {
 #pragma unroll
             for (int m = 0; m < NSW; ++m) {
                 const int c = (m * ZR) / N2, zo = (m * ZR) % N2;
-                sh[lb[c] + zo + zo / 16] = kl < ncol ? gb[(int64_t)c * A.specN + (int64_t)zo * sz] : cpx<T>{0, 0};
+                sh[lb[c] + lds_pos<ILV>(zo)] = kl < ncol ? gb[(int64_t)c * A.specN + (int64_t)zo * sz] : cpx<T>{0, 0};
             }
         }
         __syncthreads();
-        fft_lines<T, N2, NL, 512, false>(sh, tw, 3 * tk, tid);
+        fft_lines<T, N2, NL, 512, false, ILV>(sh, tw, 3 * tk, tid);
         if (kl < ncol) {
             const int kx = kx0 + kl;
             const T s0 = h0[2 * kx], c0 = h0[2 * kx + 1], s1 = h1[2 * ky], c1 = h1[2 * ky + 1];
             const double wk = (kx == 0 || 2 * kx == A.n0) ? 1.0 : 2.0;
 #pragma unroll
             for (int m = 0; m < NZ; ++m) {
-                const int zz = z0 + m * ZR, off = m * ZR + m * ZR / 16;
+                const int zz = z0 + m * ZR, off = lds_pos<ILV>(m * ZR);
                 cpx<T> fv[3];
 #pragma unroll
                 for (int c = 0; c < 3; ++c) fv[c] = sh[lb[c] + off];
@@ -937,12 +946,12 @@ __global__ __launch_bounds__(512) void k_fft_z_t(FftArgs A, const cpx<T> *tw, co
             }
         }
         __syncthreads();
-        fft_lines<T, N2, NL, 512, true>(sh, tw, 3 * tk, tid);
+        fft_lines<T, N2, NL, 512, true, ILV>(sh, tw, 3 * tk, tid);
         if (kl < ncol) {
 #pragma unroll
             for (int m = 0; m < NSW; ++m) {
                 const int c = (m * ZR) / N2, zo = (m * ZR) % N2;
-                gb[(int64_t)c * A.specN + (int64_t)zo * sz] = sh[lb[c] + zo + zo / 16];
+                gb[(int64_t)c * A.specN + (int64_t)zo * sz] = sh[lb[c] + lds_pos<ILV>(zo)];
             }
         }
     } else {
@@ -950,17 +959,17 @@ __global__ __launch_bounds__(512) void k_fft_z_t(FftArgs A, const cpx<T> *tw, co
             const int k = idx % TK, rest = idx / TK;
             const int zz = rest % N2, c = rest / N2;
             if (k < tk)
-                sh[(c * tk + k) * LS + fft_pad(zz)] = k < ncol ? base[(int64_t)c * A.specN + zz * sz + k] : cpx<T>{0, 0};
+                sh[(c * tk + k) * LS + lds_pos<ILV>(zz)] = k < ncol ? base[(int64_t)c * A.specN + zz * sz + k] : cpx<T>{0, 0};
         }
         __syncthreads();
-        fft_lines<T, N2, NL, 512, false>(sh, tw, 3 * tk, tid);
+        fft_lines<T, N2, NL, 512, false, ILV>(sh, tw, 3 * tk, tid);
         for (int idx = tid; idx < TK * N2; idx += 512) {
             const int k = idx % TK, zz = idx / TK;
             const int kx = kx0 + k;
             if (k < ncol) {
                 cpx<T> fv[3];
 #pragma unroll
-                for (int c = 0; c < 3; ++c) fv[c] = sh[(c * tk + k) * LS + fft_pad(zz)];
+                for (int c = 0; c < 3; ++c) fv[c] = sh[(c * tk + k) * LS + lds_pos<ILV>(zz)];
                 const cpx<T> f0[3] = {fv[0], fv[1], fv[2]};
                 green_apply<T>(h0[2 * kx], h0[2 * kx + 1], h1[2 * ky], h1[2 * ky + 1], h2[2 * zz], h2[2 * zz + 1],
                                fv, kx == 0 && ky == 0 && zz == 0);
@@ -970,17 +979,17 @@ __global__ __launch_bounds__(512) void k_fft_z_t(FftArgs A, const cpx<T> *tw, co
                     fv[c].x *= scale;
                     fv[c].y *= scale;
                     q += (double)f0[c].x * (double)fv[c].x + (double)f0[c].y * (double)fv[c].y;
-                    sh[(c * tk + k) * LS + fft_pad(zz)] = fv[c];
+                    sh[(c * tk + k) * LS + lds_pos<ILV>(zz)] = fv[c];
                 }
                 part += ((kx == 0 || 2 * kx == A.n0) ? 1.0 : 2.0) * q;
             }
         }
         __syncthreads();
-        fft_lines<T, N2, NL, 512, true>(sh, tw, 3 * tk, tid);
+        fft_lines<T, N2, NL, 512, true, ILV>(sh, tw, 3 * tk, tid);
         for (int idx = tid; idx < NE; idx += 512) {
             const int k = idx % TK, rest = idx / TK;
             const int zz = rest % N2, c = rest / N2;
-            if (k < ncol) base[(int64_t)c * A.specN + zz * sz + k] = sh[(c * tk + k) * LS + fft_pad(zz)];
+            if (k < ncol) base[(int64_t)c * A.specN + zz * sz + k] = sh[(c * tk + k) * LS + lds_pos<ILV>(zz)];
         }
     }
     double pv[1] = {part};
@@ -1031,7 +1040,7 @@ static bool ztmpl_size(int n) { return plane_size(n) || n == 256; }
 
 template <typename T> static bool plane_path(const Geometry &g) {
     return g.n0 == g.n1 && plane_size(g.n0) &&
-           (size_t)(g.n0 / 2 + 1) * fft_ls(g.n0) * sizeof(cpx<T>) <= (size_t)160 * 1024;
+           (size_t)(g.n0 / 2 + 1) * lds_ls<true>(g.n0) * sizeof(cpx<T>) <= (size_t)160 * 1024;
 }
 // kx columns per z-pass workgroup: 3 x TK lines of n2 complex values in LDS
 // (about 50 KB, three workgroups per CU)
@@ -1086,7 +1095,7 @@ template <typename T, int N2>
 static void zpass(const xfft_problem *p, FftArgs A, int nrhs, hipStream_t s, const Tables<T> &tb, cpx<T> *spec,
                   int64_t sz, int64_t sy) {
     constexpr int TK = tkz_t<T>(N2);
-    const size_t lds = (size_t)3 * TK * fft_ls(N2) * sizeof(cpx<T>);
+    const size_t lds = (size_t)3 * TK * lds_ls<3 * TK >= 32>(N2) * sizeof(cpx<T>);
     static bool init = false;
     if (!init) { allow_lds(k_fft_z_t<T, N2, TK>, lds); init = true; }
     const int64_t grid = (int64_t)green_blocks<T>(p->g) * nrhs;

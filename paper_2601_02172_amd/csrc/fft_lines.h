@@ -1,15 +1,25 @@
 // Compile-time LDS Stockham FFT of up to NL lines of length N (radices 16, 8, 4, 2, 3).
 //
-// Line l occupies buf[l * fft_ls(N) + fft_pad(e)], e = 0 .. N-1: one padding
-// element after every 16 keeps the stride-R stores of the early Stockham stages
-// off a single LDS bank, and the odd line stride separates lines.  Every stage
-// a thread loads the R inputs of up to MB butterflies, applies the twiddles
-// exp(-+2 pi i r k / (Ns R)) (stage-major table tw, see fft_stage_index), runs the
-// radix-R DFT in registers, and after a barrier stores the outputs in autosort
-// (Stockham) order; all index arithmetic is by compile-time constants.  The
-// power-of-two part uses as few stages as possible (radix 16 where that saves
-// a stage over radix 8), since every stage costs an LDS round trip and a
-// twiddle multiplication per point.
+// Every stage a thread loads the R inputs of up to MB butterflies, applies the
+// twiddles exp(-+2 pi i r k / (Ns R)) (stage-major table tw, see
+// fft_stage_index), runs the radix-R DFT in registers, and after a barrier
+// stores the outputs in autosort (Stockham) order; all index arithmetic is by
+// compile-time constants.  The power-of-two part uses as few stages as
+// possible (radix 16 where that saves a stage over radix 8), since every stage
+// costs an LDS round trip and a twiddle multiplication per point.
+//
+// Two LDS layouts.  The LDS serves the 32 lanes of a half wave per pass, and an
+// access of 8 or 16 bytes per lane is conflict free when the element indices
+// of those lanes are distinct modulo 32 (8-byte elements) or cover each
+// residue modulo 16 at most twice (16-byte elements).
+//  * padded (ILV = false): line l at buf[l * fft_ls(N) + fft_pad(e)], one
+//    padding element after every 16, butterflies numbered line by line.  Used
+//    where a workgroup holds few lines.
+//  * interleaved (ILV = true): line l at buf[l * (N | 1) + e], and the lanes of
+//    a half wave take the same butterfly of 32 consecutive lines, so every
+//    load and store of a stage touches 32 different lines at one offset: with
+//    the odd line stride these are 32 different banks.  Lines beyond the last
+//    complete group of 32 are numbered line by line.
 #pragma once
 
 #include "common.h"
@@ -18,6 +28,10 @@ namespace xfft {
 
 __host__ __device__ constexpr int fft_pad(int e) { return e + (e >> 4); }
 __host__ __device__ constexpr int fft_ls(int n) { return ((n + (n >> 4)) | 1); }   // odd line stride
+
+// line stride and element position of the two layouts
+template <bool ILV> __host__ __device__ constexpr int lds_ls(int n) { return ILV ? (n | 1) : fft_ls(n); }
+template <bool ILV> __host__ __device__ constexpr int lds_pos(int e) { return ILV ? e : fft_pad(e); }
 
 __host__ __device__ constexpr int fft_radix(int n, int stage) {
     int a = 0, m = n;
@@ -157,33 +171,47 @@ __device__ __forceinline__ void dft_small(cpx<T> (&v)[16]) {
 // one LDS address and the R accesses use constant offsets.
 template <int M> __host__ __device__ constexpr int pad_step(int r) { return r * M + ((r * M) >> 4); }
 
-template <typename T, int N, int NL, int NT, bool INV, int STAGE = 0, int NS = 1>
+template <typename T, int N, int NL, int NT, bool INV, bool ILV = false, int STAGE = 0, int NS = 1>
 __device__ __forceinline__ void fft_lines(cpx<T> *buf, const cpx<T> *__restrict__ tw, int nl = NL,
                                           int tid = threadIdx.x) {
     constexpr int R = fft_radix(N, STAGE);
     if constexpr (R != 0) {
-        constexpr int LS = fft_ls(N);
+        constexpr int LS = lds_ls<ILV>(N);
         constexpr int NB = N / R;
         constexpr int TOTAL = NL * NB;
         constexpr int MB = (TOTAL + NT - 1) / NT;
-        constexpr bool P2 = (NB & (NB - 1)) == 0 && (NS & (NS - 1)) == 0;
+        // constant load and store offsets: always in the interleaved layout,
+        // for power-of-two NB and NS in the padded one
+        constexpr bool P2 = ILV || ((NB & (NB - 1)) == 0 && (NS & (NS - 1)) == 0);
         const int total = nl * NB;          // lines nl .. NL-1 are skipped
+        const int full = ILV ? (nl & ~31) * NB : 0;   // butterflies of complete 32-line groups
         cpx<T> v[MB][16];
-        int st[MB];                         // padded LDS position of each butterfly's first output
+        int st[MB];                         // LDS position of each butterfly's first output
 #pragma unroll
         for (int i = 0; i < MB; ++i) {
             const int b = tid + i * NT;
             st[i] = 0;
             if ((TOTAL % NT == 0 && nl == NL) || b < total) {
-                const int line = b / NB, jj = b - line * NB;
+                int line, jj;
+                if (ILV && b < full) {
+                    const int g = b >> 5;
+                    jj = g % NB;
+                    line = (g / NB) * 32 + (b & 31);
+                } else {
+                    const int bb = b - full;
+                    line = full / NB + bb / NB;
+                    jj = bb % NB;
+                }
                 const int k = jj % NS;
                 const int base = (jj / NS) * NS * R + k;
-                const int ld = line * LS + fft_pad(jj);
-                st[i] = line * LS + fft_pad(base);
+                const int ld = line * LS + lds_pos<ILV>(jj);
+                st[i] = line * LS + lds_pos<ILV>(base);
                 const cpx<T> *twk = tw + (NS - 1) + k * (R - 1) - 1;   // twk[r], r >= 1
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
-                    cpx<T> x = P2 ? buf[ld + pad_step<NB>(r)] : buf[line * LS + fft_pad(jj + r * NB)];
+                    cpx<T> x = ILV ? buf[ld + r * NB]
+                             : P2  ? buf[ld + pad_step<NB>(r)]
+                                   : buf[line * LS + fft_pad(jj + r * NB)];
                     if (NS > 1 && r > 0) {
                         cpx<T> w = twk[r];
                         if (INV) w.y = -w.y;
@@ -199,7 +227,10 @@ __device__ __forceinline__ void fft_lines(cpx<T> *buf, const cpx<T> *__restrict_
         for (int i = 0; i < MB; ++i) {
             const int b = tid + i * NT;
             if ((TOTAL % NT == 0 && nl == NL) || b < total) {
-                if constexpr (P2) {
+                if constexpr (ILV) {
+#pragma unroll
+                    for (int r = 0; r < R; ++r) buf[st[i] + r * NS] = v[i][r];
+                } else if constexpr (P2) {
 #pragma unroll
                     for (int r = 0; r < R; ++r) buf[st[i] + pad_step<NS>(r)] = v[i][r];
                 } else {
@@ -211,7 +242,7 @@ __device__ __forceinline__ void fft_lines(cpx<T> *buf, const cpx<T> *__restrict_
             }
         }
         __syncthreads();
-        fft_lines<T, N, NL, NT, INV, STAGE + 1, NS * R>(buf, tw, nl, tid);
+        fft_lines<T, N, NL, NT, INV, ILV, STAGE + 1, NS * R>(buf, tw, nl, tid);
     }
 }
 
