@@ -643,6 +643,9 @@ int xfft_setup(const int32_t n[3], const double len[3], const double *levelset, 
     if (!n || !len || !levelset || !phase || !lame || nphase < 1) return XFFT_EINVAL;
     for (int a = 0; a < 3; ++a)
         if (!size_ok(n[a]) || !(len[a] > 0.0) || !std::isfinite(len[a])) return XFFT_EINVAL;
+    // the operator addresses the three components of a field of one load with
+    // 32-bit byte offsets
+    if ((int64_t)n[0] * n[1] * n[2] * 3 * (int64_t)sizeof(double) >= ((int64_t)1 << 32)) return XFFT_EINVAL;
     const double h = len[0] / n[0];
     for (int a = 1; a < 3; ++a)
         if (std::fabs(len[a] / n[a] - h) > 1e-12 * h) return XFFT_EINVAL;
@@ -700,6 +703,8 @@ int xfft_setup(const int32_t n[3], const double len[3], const double *levelset, 
         rc = XFFT_EDEVICE;
     if (!rc) rc = run_setup(p, Lraw);
     if (Lraw) (void)hipFree(Lraw);
+    // and the corner-force buffer of one load (24 values per irregular voxel) likewise
+    if (!rc && g.nirr * 24 * (int64_t)sizeof(double) >= ((int64_t)1 << 32)) rc = XFFT_EINVAL;
     if (!rc) rc = compute_tables(p);
     if (!rc) {
         for (int a = 0; a < 3; ++a)

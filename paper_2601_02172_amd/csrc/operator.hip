@@ -12,6 +12,7 @@
 //  k_enriched   one thread per enriched node; sums the buffered enriched
 //               corner forces of its (at most eight) irregular voxels.
 #include "kernels.h"
+#include <type_traits>
 #include "element.h"
 
 namespace xfft {
@@ -23,6 +24,12 @@ constexpr int TO = TE - 1;      // owned nodes per tile edge
 constexpr int TC = TE + 1;      // node columns per tile edge (halo on the + side)
 
 __device__ __forceinline__ int wrapi(int a, int n) { return a < 0 ? a + n : (a >= n ? a - n : a); }
+
+// base[i] with a 32-bit byte offset (uniform base pointer + 32-bit lane offset)
+template <typename P> __device__ __forceinline__ P &elem(P *base, uint32_t i) {
+    using B = typename std::conditional<std::is_const<P>::value, const char, char>::type;
+    return *reinterpret_cast<P *>(reinterpret_cast<B *>(base) + (uint32_t)(i * (uint32_t)sizeof(P)));
+}
 
 template <typename T>
 struct OpArgs {
@@ -179,7 +186,7 @@ __device__ __forceinline__ double dpp_row_shr1(double v) {
 template <typename T, bool HX, bool EB, bool ST>
 __global__ __launch_bounds__(256) void k_regular(OpArgs<T> A) {
     __shared__ T Dp[3][TC * TC][3];
-    __shared__ T FB[2][6][TE * TE];    // row sums for the node above, double-buffered by layer parity
+    __shared__ T FB[3][6][TE * TE];    // row sums for the node above, one buffer per layer of the unrolled march
     __shared__ double red[4 * 7];
 
     // logical block: (rhs, z chunk, tile y, tile x), x fastest
@@ -194,16 +201,19 @@ __global__ __launch_bounds__(256) void k_regular(OpArgs<T> A) {
     const int n0 = A.n0, n1 = A.n1, n2 = A.n2;
     const int64_t N = A.N, plane_sz = (int64_t)n0 * n1;
     const int a = i0 - 1 + tx, b = j0 - 1 + ty;
-    // tiles may wrap more than once around small grids: full modulo here, once
+    // tiles may wrap more than once around small grids: full modulo here, once.
+    // Offsets are 32-bit from per-load base pointers (3 N values of T and the
+    // corner-force buffer of one load stay below 2^32 bytes, checked at setup).
     const int aw = ((a % n0) + n0) % n0, bw = ((b % n1) + n1) % n1;
-    const int64_t colv = aw + (int64_t)n0 * bw;
-    int64_t colxy[2];
+    const uint32_t N32 = (uint32_t)N, psz = (uint32_t)n0 * (uint32_t)n1;
+    const uint32_t colv = (uint32_t)aw + (uint32_t)n0 * (uint32_t)bw;
+    uint32_t colxy[2];
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
         const int col = tid + 256 * u;
         const int cx = col % TC, cy = col / TC;
         const int xi = (((i0 - 1 + cx) % n0) + n0) % n0, yi = (((j0 - 1 + cy) % n1) + n1) % n1;
-        colxy[u] = xi + (int64_t)n0 * yi;
+        colxy[u] = (uint32_t)xi + (uint32_t)n0 * (uint32_t)yi;
     }
     const bool owner = tx >= 1 && ty >= 1 && a < n0 && b < n1;
 
@@ -218,21 +228,24 @@ __global__ __launch_bounds__(256) void k_regular(OpArgs<T> A) {
     }
     double acc7[7] = {0, 0, 0, 0, 0, 0, 0};
     double *vs = A.vstress ? A.vstress + (int64_t)r * 6 * N : nullptr;
+    auto plane_off = [&](int kk) { return psz * (uint32_t)wrapi(kk, n2); };
 
-    // plane loads go through registers two planes ahead of their use, so that
-    // the loads of plane kl + 3 are in flight while layer kl is computed and
-    // plane kl + 2 (loaded one layer earlier) is stored to LDS
-    T pre[2][3], pfar[2][3];
+    // Plane loads go through a ring of three register buffers: the loads of
+    // plane kl + 3 are in flight while layer kl is computed and plane kl + 2
+    // (loaded one layer earlier) is stored to LDS.  The march is unrolled by
+    // three layers, so LDS slots, register buffers and exchange buffers are
+    // compile-time indices.
+    T R[3][2][3];
     auto fetch_plane = [&](int kk, T (&dst)[2][3]) {
         if constexpr (HX) {
-            const int64_t off = plane_sz * wrapi(kk, n2);
+            const uint32_t off = plane_off(kk);
 #pragma unroll
             for (int u = 0; u < 2; ++u) {
                 if (tid + 256 * u < TC * TC) {
-                    const int64_t node = colxy[u] + off;
-                    dst[u][0] = x[node];
-                    dst[u][1] = x[N + node];
-                    dst[u][2] = x[2 * N + node];
+                    const uint32_t node = colxy[u] + off;
+                    dst[u][0] = elem(x, node);
+                    dst[u][1] = elem(x, N32 + node);
+                    dst[u][2] = elem(x, 2 * N32 + node);
                 }
             }
         }
@@ -251,31 +264,37 @@ __global__ __launch_bounds__(256) void k_regular(OpArgs<T> A) {
         }
     };
 
-    fetch_plane(k0 - 1, pre);
-    store_plane(0, pre);
-    fetch_plane(k0, pre);
-    store_plane(1, pre);
-    if (k0 + 1 <= k1) fetch_plane(k0 + 1, pre);
-    int m = A.vmat[colv + plane_sz * wrapi(k0 - 1, n2)];
-    int m_next = (k0 < k1) ? A.vmat[colv + plane_sz * wrapi(k0, n2)] : 0;
+    fetch_plane(k0 - 1, R[0]);
+    store_plane(0, R[0]);
+    fetch_plane(k0, R[1]);
+    store_plane(1, R[1]);
+    if (k0 + 1 <= k1) fetch_plane(k0 + 1, R[2]);
+    int mv[3];                       // material / irregular index of the voxel at layers kl, kl + 1, kl + 2
+    mv[0] = elem(A.vmat, colv + plane_off(k0 - 1));
+    mv[1] = (k0 < k1) ? elem(A.vmat, colv + plane_off(k0)) : 0;
+    mv[2] = 0;
     __syncthreads();
 
     T acc[3] = {0, 0, 0};
-    for (int s = 0, kl = k0 - 1; kl < k1; ++s, ++kl) {
-        const int sb = s % 3, st = (s + 1) % 3;
+    // layer s (kl = k0 - 1 + s) uses LDS planes in slots sb (kl) and st (kl + 1)
+    // and stores plane kl + 2 to slot sn
+    auto layer = [&](auto slot_tag, int s) {
+        constexpr int sb = decltype(slot_tag)::value, st = (sb + 1) % 3, sn = (sb + 2) % 3;
+        const int kl = k0 - 1 + s;
         const bool more = kl + 2 <= k1, more2 = kl + 3 <= k1;
-        if (more2) fetch_plane(kl + 3, pfar);
-        const int m_far = (kl + 2 < k1) ? A.vmat[colv + plane_sz * wrapi(kl + 2, n2)] : 0;
-        const int64_t vox = colv + plane_sz * wrapi(kl, n2);
+        if (more2) fetch_plane(kl + 3, R[sb]);
+        mv[sn] = (kl + 2 < k1) ? elem(A.vmat, colv + plane_off(kl + 2)) : 0;
+        const int m = mv[sb];
+        const uint32_t vox = colv + plane_off(kl);
         T F[8][3];
         if (m < 0) {
             // buffered corner forces of an irregular voxel: the loads are issued
             // before the regular lanes compute, so their latency is overlapped
-            const T *cb = cutbuf + (int64_t)(-m - 1) * 24;
+            const uint32_t cq = (uint32_t)(-m - 1) * 24u;
 #pragma unroll
             for (int c = 0; c < 8; ++c)
 #pragma unroll
-                for (int i = 0; i < 3; ++i) F[c][i] = cb[3 * c + i];
+                for (int i = 0; i < 3; ++i) F[c][i] = elem(cutbuf, cq + 3 * c + i);
         }
         if (m >= 0) {
             T U[8][3];
@@ -292,43 +311,42 @@ __global__ __launch_bounds__(256) void k_regular(OpArgs<T> A) {
             regular_voxel<T, EB, ST>(U, eb, lamV, muV, F, S);
             if (ST && owner && kl >= k0) {
                 add_sym(acc7, S);
-                if (vs) store_vstress(vs, N, vox, S);
+                if (vs) store_vstress(vs, N, (int64_t)vox, S);
             }
         }
         // Corner sums of node (a, b): own corner 0 (4), corner 1 (5) of the voxel
         // at a - 1 (lane tx - 1 of the same 16-lane row, moved by DPP), and the
         // row sum "corner 2 (6) + left neighbour's corner 3 (7)" of the thread
         // at b - 1, exchanged through LDS.
-        const int fb = s & 1;
         T bot[3], top[3];
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
             bot[i] = F[0][i] + dpp_row_shr1(F[1][i]);
             top[i] = F[4][i] + dpp_row_shr1(F[5][i]);
-            FB[fb][i][tid] = F[2][i] + dpp_row_shr1(F[3][i]);
-            FB[fb][3 + i][tid] = F[6][i] + dpp_row_shr1(F[7][i]);
+            FB[sb][i][tid] = F[2][i] + dpp_row_shr1(F[3][i]);
+            FB[sb][3 + i][tid] = F[6][i] + dpp_row_shr1(F[7][i]);
         }
         T dv[3] = {0, 0, 0};
         if constexpr (HX) {
 #pragma unroll
             for (int i = 0; i < 3; ++i) dv[i] = Dp[sb][tx + TC * ty][i];
         }
-        if (more) store_plane((s + 2) % 3, pre);
-        // one barrier per layer: the row sums are double-buffered, the Dp slot
-        // written next layer was last read before this barrier
+        if (more) store_plane(sn, R[sn]);
+        // one barrier per layer: the row sums rotate through three buffers, and
+        // the Dp slot written next layer was last read before this barrier
         __syncthreads();
         if (owner) {
 #pragma unroll
             for (int i = 0; i < 3; ++i) {
-                bot[i] += FB[fb][i][tid - 16];
-                top[i] += FB[fb][3 + i][tid - 16];
+                bot[i] += FB[sb][i][tid - 16];
+                top[i] += FB[sb][3 + i][tid - 16];
             }
             if (kl >= k0) {
                 T dot = 0;                 // three terms in T, summed over the column in FP64
 #pragma unroll
                 for (int i = 0; i < 3; ++i) {
                     const T out = A.sign * (acc[i] + bot[i]);
-                    y[i * N + vox] = out;
+                    elem(y, (uint32_t)i * N32 + vox) = out;
                     if constexpr (HX) dot += out * dv[i];
                 }
                 acc7[0] += (double)dot;
@@ -336,14 +354,12 @@ __global__ __launch_bounds__(256) void k_regular(OpArgs<T> A) {
 #pragma unroll
             for (int i = 0; i < 3; ++i) acc[i] = top[i];
         }
-        m = m_next;
-        m_next = m_far;
-        if (more2) {
-#pragma unroll
-            for (int u = 0; u < 2; ++u)
-#pragma unroll
-                for (int i = 0; i < 3; ++i) pre[u][i] = pfar[u][i];
-        }
+    };
+    const int nlayer = k1 - k0 + 1;
+    for (int s = 0; s < nlayer; s += 3) {
+        layer(std::integral_constant<int, 0>{}, s);
+        if (s + 1 < nlayer) layer(std::integral_constant<int, 1>{}, s + 1);
+        if (s + 2 < nlayer) layer(std::integral_constant<int, 2>{}, s + 2);
     }
     __syncthreads();
     block_sum<7>(acc7, red);

@@ -52,7 +52,7 @@ def _setup_rc(n, length, L, ph, lame):
     return rc
 
 
-@pytest.mark.parametrize("case", ["odd", "prime", "small", "noncubic", "nan", "phase", "mu", "bulk"])
+@pytest.mark.parametrize("case", ["odd", "prime", "small", "noncubic", "nan", "phase", "mu", "bulk", "huge"])
 def test_setup_rejects_invalid_input(case):
     n = [8, 8, 8]
     length = [8.0, 8.0, 8.0]
@@ -79,6 +79,10 @@ def test_setup_rejects_invalid_input(case):
         lame = np.array([[1.0, 0.0]])
     elif case == "bulk":
         lame = np.array([[-1.0, 0.5]])
+    elif case == "huge":
+        # 3 N doubles of one load above 4 GiB: rejected before the level set is read
+        n = [1024, 1024, 1024]
+        length = [1024.0] * 3
     assert _setup_rc(n, length, L, ph, lame) == X.XFFT_EINVAL
 
 
