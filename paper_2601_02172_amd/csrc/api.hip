@@ -3,6 +3,7 @@
 // operator / preconditioner applications.
 #include "../../include/xfft.h"
 #include "kernels.h"
+#include "enriched.h"
 
 #include <chrono>
 #include <cmath>
@@ -117,21 +118,17 @@ void cg_iteration(xfft_problem *p, Work<T> &w, const Tables<T> &tb, int nrhs, in
     // the stress integral is only needed when the criterion tracks <sigma> (criterion 0)
     launch_operator<T>(p, w, tb, w.d, w.de, w.z, w.ze, false, (T)1, nrhs, p->flags, parity, nullptr, s, crit == 0);
     launch_scalars(p, SC_ALPHA, crit, nrhs, parity, nullptr, s, sizeof(T) == 8);
-    launch_green_forward<T>(p, w, tb, w.f, w.z, nrhs, p->flags, parity, s);
-    launch_enr_update<T>(p, w, 1, nullptr, nrhs, p->flags, parity, s);
+    launch_green_forward<T>(p, w, tb, w.f, w.z, nrhs, p->flags, parity, s, 1, nullptr);
     launch_scalars(p, SC_BETA, crit, nrhs, parity, nullptr, s, sizeof(T) == 8);
-    launch_green_inverse<T>(p, w, tb, 1, nullptr, nrhs, p->flags, parity, s);
-    launch_enr_final<T>(p, w, 1, nrhs, p->flags, parity, s);
+    launch_green_inverse<T>(p, w, tb, 1, nullptr, nrhs, p->flags, parity, s, 1);
 }
 
 // Initial preconditioned residual: d = P^-1 f, res2, convergence flags.
 template <typename T>
 void cg_start(xfft_problem *p, Work<T> &w, const Tables<T> &tb, int nrhs, int crit) {
     hipStream_t s = p->stream;
-    launch_green_forward<T>(p, w, tb, w.f, nullptr, nrhs, nullptr, 0, s);
-    launch_enr_update<T>(p, w, 0, nullptr, nrhs, nullptr, 0, s);
-    launch_green_inverse<T>(p, w, tb, 2, nullptr, nrhs, nullptr, 0, s);
-    launch_enr_final<T>(p, w, 2, nrhs, nullptr, 0, s);
+    launch_green_forward<T>(p, w, tb, w.f, nullptr, nrhs, nullptr, 0, s, 0, nullptr);
+    launch_green_inverse<T>(p, w, tb, 2, nullptr, nrhs, nullptr, 0, s, 2);
     launch_scalars(p, SC_INIT_RES, crit, nrhs, 0, nullptr, s, sizeof(T) == 8);
 }
 
@@ -715,7 +712,7 @@ int xfft_setup(const int32_t n[3], const double len[3], const double *levelset, 
         L.grn0 = L.total;
         L.grn_n = green_slots(g);
         L.eu0 = L.grn0 + L.grn_n;
-        L.eu_n = (int)((g.nX + 255) / 256);
+        L.eu_n = (int)((g.nX + ENR_BLOCK - 1) / ENR_BLOCK);
         L.total = L.eu0 + L.eu_n;
         p->slots = L;
         p->nslots = L.total;
@@ -842,9 +839,8 @@ int xfft_apply_precond(xfft_problem *p, int32_t precision, const double *f, doub
         Work<double> &w = p->w64;
         HIP_OK(hipMemcpyAsync(w.f, f, sizeof(double) * 3 * N, hipMemcpyHostToDevice, s));
         if (nX) HIP_OK(hipMemcpyAsync(w.fe, f + 3 * N, sizeof(double) * 3 * nX, hipMemcpyHostToDevice, s));
-        launch_green_forward<double>(p, w, p->t64, w.f, nullptr, 1, nullptr, 0, s);
-        launch_enr_update<double>(p, w, 0, w.ze, 1, nullptr, 0, s);
-        launch_green_inverse<double>(p, w, p->t64, 0, w.z, 1, nullptr, 0, s);
+        launch_green_forward<double>(p, w, p->t64, w.f, nullptr, 1, nullptr, 0, s, 0, w.ze);
+        launch_green_inverse<double>(p, w, p->t64, 0, w.z, 1, nullptr, 0, s, 0);
         launch_scalars(p, SC_SUM_GREEN, 0, 1, 0, sum_dev, s, true);
         HIP_OK(hipMemcpyAsync(y, w.z, sizeof(double) * 3 * N, hipMemcpyDeviceToHost, s));
         if (nX) HIP_OK(hipMemcpyAsync(y + 3 * N, w.ze, sizeof(double) * 3 * nX, hipMemcpyDeviceToHost, s));
@@ -854,9 +850,8 @@ int xfft_apply_precond(xfft_problem *p, int32_t precision, const double *f, doub
         for (size_t q = 0; q < ff.size(); ++q) ff[q] = (float)f[q];
         HIP_OK(hipMemcpyAsync(w.f, ff.data(), sizeof(float) * 3 * N, hipMemcpyHostToDevice, s));
         if (nX) HIP_OK(hipMemcpyAsync(w.fe, ff.data() + 3 * N, sizeof(float) * 3 * nX, hipMemcpyHostToDevice, s));
-        launch_green_forward<float>(p, w, p->t32, w.f, nullptr, 1, nullptr, 0, s);
-        launch_enr_update<float>(p, w, 0, w.ze, 1, nullptr, 0, s);
-        launch_green_inverse<float>(p, w, p->t32, 0, w.z, 1, nullptr, 0, s);
+        launch_green_forward<float>(p, w, p->t32, w.f, nullptr, 1, nullptr, 0, s, 0, w.ze);
+        launch_green_inverse<float>(p, w, p->t32, 0, w.z, 1, nullptr, 0, s, 0);
         launch_scalars(p, SC_SUM_GREEN, 0, 1, 0, sum_dev, s, false);
         HIP_OK(hipMemcpyAsync(yf.data(), w.z, sizeof(float) * 3 * N, hipMemcpyDeviceToHost, s));
         if (nX) HIP_OK(hipMemcpyAsync(yf.data() + 3 * N, w.ze, sizeof(float) * 3 * nX, hipMemcpyDeviceToHost, s));

@@ -7,6 +7,7 @@
 // normalised by |Y|): crit 0: sqrt(res2 / |Y|) <= tol ||<sigma>||; crit 1
 // (inner solves of iterative refinement): res2 <= tol^2 res2_0.
 #include "kernels.h"
+#include "enriched.h"
 
 namespace xfft {
 
@@ -100,55 +101,20 @@ __global__ __launch_bounds__(256) void k_scalars(ScArgs A) {
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_enr_update(int64_t nX, const Flags *flags, int parity, const Scalars *scal,
-                                                     int mode, T *fe, const T *ze, T *out, double *partial,
-                                                     int nslots, int slot0) {
-    __shared__ double red[4];
+__global__ __launch_bounds__(ENR_BLOCK) void k_enr_update(EnrUpd<T> E, const Flags *flags, int parity,
+                                                           const Scalars *scal, double *partial, int nslots) {
+    __shared__ double red[ENR_BLOCK / 64];
     const int r = blockIdx.y;
     if (flags && !flags[r].active[parity]) return;
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    double acc[1] = {0.0};
-    if (j < nX) {
-        const T alpha = (T)scal[r].alpha;
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            const int64_t o = (int64_t)r * 3 * nX + c * nX + j;
-            T v = fe[o];
-            if (mode == 1) {
-                v -= alpha * ze[o];
-                fe[o] = v;
-            }
-            if (out) out[o] = v;
-            acc[0] += (double)v * (double)v;
-        }
-    }
-    block_sum<1>(acc, red);
-    if (threadIdx.x == 0) {
-        double *P = partial + ((int64_t)r * nslots + slot0 + blockIdx.x) * NPART;
-        P[0] = acc[0];
-        for (int q = 1; q < 7; ++q) P[q] = 0.0;
-    }
+    enr_update_block<T>(E, scal, partial, nslots, r, blockIdx.x, red);
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_enr_final(int64_t nX, const Flags *flags, int parity, const Scalars *scal,
-                                                    int mode, T *ue, T *de, const T *fe) {
+__global__ __launch_bounds__(256) void k_enr_final(EnrFin<T> E, const Flags *flags, int parity, const Scalars *scal) {
     const int r = blockIdx.y;
     if (flags && !flags[r].active[parity]) return;
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= nX) return;
-    const T alpha = (T)scal[r].alpha, beta = (T)scal[r].beta;
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        const int64_t o = (int64_t)r * 3 * nX + c * nX + j;
-        if (mode == 1) {
-            const T d = de[o];
-            ue[o] += alpha * d;
-            de[o] = fe[o] + beta * d;
-        } else {
-            de[o] = fe[o];
-        }
-    }
+    enr_final_rows<T>(E, scal, r, j, E.nX);
 }
 
 // iterative refinement: w32.f <- (float) w64.f, w32.u <- 0 for RHS whose outer loop runs
@@ -202,13 +168,37 @@ void launch_scalars(xfft_problem *p, int op, int crit, int nrhs, int parity, dou
 }
 
 template <typename T>
+EnrUpd<T> enr_update_args(xfft_problem *p, Work<T> &w, int mode, T *out) {
+    EnrUpd<T> E;
+    E.nX = p->g.nX;
+    E.mode = mode;
+    E.fe = w.fe;
+    E.ze = w.ze;
+    E.out = out;
+    E.nblk = p->slots.eu_n;
+    E.slot0 = p->slots.eu0;
+    return E;
+}
+
+template <typename T>
+EnrFin<T> enr_final_args(xfft_problem *p, Work<T> &w, int mode) {
+    EnrFin<T> E;
+    E.nX = p->g.nX;
+    E.mode = mode;
+    E.ue = w.ue;
+    E.de = w.de;
+    E.fe = w.fe;
+    return E;
+}
+
+template <typename T>
 void launch_enr_update(xfft_problem *p, Work<T> &w, int mode, T *out, int nrhs, const Flags *flags, int parity,
                        hipStream_t s) {
     if (p->g.nX == 0) return;
     dim3 grid(p->slots.eu_n, nrhs);
     xfft_prof_mark(p, -1, s);
-    k_enr_update<T><<<grid, 256, 0, s>>>(p->g.nX, flags, parity, p->scal, mode, w.fe, w.ze, out, p->partial,
-                                         p->nslots, p->slots.eu0);
+    k_enr_update<T><<<grid, ENR_BLOCK, 0, s>>>(enr_update_args<T>(p, w, mode, out), flags, parity, p->scal,
+                                               p->partial, p->nslots);
     xfft_prof_mark(p, K_ENR_UPDATE + (sizeof(T) == 8 ? K_COUNT : 0), s);
 }
 
@@ -218,10 +208,14 @@ void launch_enr_final(xfft_problem *p, Work<T> &w, int mode, int nrhs, const Fla
     if (p->g.nX == 0) return;
     dim3 grid((unsigned)((p->g.nX + 255) / 256), nrhs);
     xfft_prof_mark(p, -1, s);
-    k_enr_final<T><<<grid, 256, 0, s>>>(p->g.nX, flags, parity, p->scal, mode, w.ue, w.de, w.fe);
+    k_enr_final<T><<<grid, 256, 0, s>>>(enr_final_args<T>(p, w, mode), flags, parity, p->scal);
     xfft_prof_mark(p, K_ENR_FINAL + (sizeof(T) == 8 ? K_COUNT : 0), s);
 }
 
+template EnrUpd<double> enr_update_args<double>(xfft_problem *, Work<double> &, int, double *);
+template EnrUpd<float> enr_update_args<float>(xfft_problem *, Work<float> &, int, float *);
+template EnrFin<double> enr_final_args<double>(xfft_problem *, Work<double> &, int);
+template EnrFin<float> enr_final_args<float>(xfft_problem *, Work<float> &, int);
 template void launch_enr_update<double>(xfft_problem *, Work<double> &, int, double *, int, const Flags *, int,
                                         hipStream_t);
 template void launch_enr_update<float>(xfft_problem *, Work<float> &, int, float *, int, const Flags *, int,

@@ -17,6 +17,7 @@
 //   phi_ab = (theta_a + theta_b) / 2, {a, b, c} = {0, 1, 2};
 // S(0) = 0 maps the zero frequency to zero (mean-free FE field).
 #include "kernels.h"
+#include "enriched.h"
 #include "fft_lines.h"
 
 namespace xfft {
@@ -748,12 +749,18 @@ __device__ __forceinline__ void plane_inverse_core(cpx<T> *sh, const cpx<T> *tw,
 // mode 0: out = G f; mode 1: u += alpha d, d = G f + beta d; mode 2: d = G f
 template <typename T, int N, bool PIPE>
 __global__ __launch_bounds__(1024) void k_fft_plane_inv(FftArgs A, const cpx<T> *tw, const cpx<T> *spec, int mode,
-                                                         T *out, T *u, T *d, int nrhs) {
+                                                         T *out, T *u, T *d, int nrhs, EnrFin<T> E) {
     using C = PlaneCfg<N>;
     extern __shared__ unsigned char smem_raw[];
     cpx<T> *sh = reinterpret_cast<cpx<T> *>(smem_raw);
     const int per_r = 3 * A.n2, total = per_r * nrhs;
     int tid = threadIdx.x;
+    if (E.mode) {
+        // enriched direction update, spread over the whole grid
+        for (int r = 0; r < nrhs; ++r)
+            if (active_rhs(A, r))
+                enr_final_rows<T>(E, A.scal, r, (int64_t)blockIdx.x * C::NT + tid, (int64_t)gridDim.x * C::NT);
+    }
     cpx<T> sp[C::PS];
     auto fetch = [&](int q) {
         const int r = q / per_r, plane = q - r * per_r;
@@ -874,7 +881,9 @@ __global__ __launch_bounds__(1024) void k_fft_plane_inv(FftArgs A, const cpx<T> 
 // different banks in the staging and Green phases too.
 template <typename T, int N2, int TK>
 __global__ __launch_bounds__(512) void k_fft_z_t(FftArgs A, const cpx<T> *tw, const T *h0, const T *h1,
-                                                  const T *h2, cpx<T> *spec, int64_t sz, int64_t sy, int nrhs) {
+                                                  const T *h2, cpx<T> *spec, int64_t sz, int64_t sy, int nrhs,
+                                                  EnrUpd<T> E) {
+    static_assert(ENR_BLOCK == 512, "the enriched workgroups use the z-pass workgroup size");
     constexpr int NL = 3 * TK;
     constexpr bool ILV = NL >= 32;
     constexpr int LS = lds_ls<ILV>(N2);
@@ -889,6 +898,12 @@ __global__ __launch_bounds__(512) void k_fft_z_t(FftArgs A, const cpx<T> *tw, co
     const int ntiles = (nh + TK - 1) / TK;
     const int nblk = A.n1 * ntiles;                 // workgroups per right-hand side
     const int tk = (nh + ntiles - 1) / ntiles;
+    if ((int)blockIdx.x >= nblk * nrhs) {
+        // enriched residual update (workgroups after the z-pass ones)
+        const int e = (int)blockIdx.x - nblk * nrhs, re = e / E.nblk;
+        if (active_rhs(A, re)) enr_update_block<T>(E, A.scal, A.partial, A.nslots, re, e - re * E.nblk, red);
+        return;
+    }
     int nact = 0;
     for (int q = 0; q < nrhs; ++q) nact += active_rhs(A, q) ? 1 : 0;
     const int total = nact * nblk;
@@ -1083,24 +1098,24 @@ static void plane_fwd(const xfft_problem *p, FftArgs A, int nrhs, hipStream_t s,
 }
 template <typename T, int N>
 static void plane_inv(const xfft_problem *p, FftArgs A, int nrhs, hipStream_t s, const cpx<T> *tw,
-                      const cpx<T> *spec, int mode, T *out, T *u, T *d) {
+                      const cpx<T> *spec, int mode, T *out, T *u, T *d, const EnrFin<T> &E) {
     constexpr bool PIPE = plane_pipe<T>();
     const size_t lds = (size_t)PlaneCfg<N>::ELEMS * sizeof(cpx<T>);
     static bool init = false;
     if (!init) { allow_lds(k_fft_plane_inv<T, N, PIPE>, lds); init = true; }
     k_fft_plane_inv<T, N, PIPE><<<plane_grid<T>(p, nrhs), PlaneCfg<N>::NT, lds, s>>>(A, tw, spec, mode, out, u, d,
-                                                                                     nrhs);
+                                                                                     nrhs, E);
 }
 template <typename T, int N2>
 static void zpass(const xfft_problem *p, FftArgs A, int nrhs, hipStream_t s, const Tables<T> &tb, cpx<T> *spec,
-                  int64_t sz, int64_t sy) {
+                  int64_t sz, int64_t sy, const EnrUpd<T> &E) {
     constexpr int TK = tkz_t<T>(N2);
     const size_t lds = (size_t)3 * TK * lds_ls<3 * TK >= 32>(N2) * sizeof(cpx<T>);
     static bool init = false;
     if (!init) { allow_lds(k_fft_z_t<T, N2, TK>, lds); init = true; }
-    const int64_t grid = (int64_t)green_blocks<T>(p->g) * nrhs;
+    const int64_t grid = ((int64_t)green_blocks<T>(p->g) + E.nblk) * nrhs;
     k_fft_z_t<T, N2, TK><<<(unsigned)grid, 512, lds, s>>>(A, tb.tws[2], tb.half[0], tb.half[1], tb.half[2], spec,
-                                                        sz, sy, nrhs);
+                                                        sz, sy, nrhs, E);
 }
 
 // compile-time x and y passes (ztmpl sizes); return false when n has no such variant
@@ -1175,8 +1190,10 @@ template <typename T, bool INV> static bool y_pass_t(const xfft_problem *p, FftA
 
 template <typename T>
 void launch_green_forward(xfft_problem *p, Work<T> &w, const Tables<T> &tb, T *f, const T *z, int nrhs,
-                          const Flags *flags, int parity, hipStream_t s) {
+                          const Flags *flags, int parity, hipStream_t s, int enr_mode, T *enr_out) {
     const Geometry &g = p->g;
+    EnrUpd<T> E = enr_update_args<T>(p, w, enr_mode, enr_out);
+    if (g.nX == 0) E.nblk = 0;
     FftArgs A = fft_args<T>(p, flags, parity);
     const bool plane = plane_path<T>(g);
     int64_t sz, sy;
@@ -1222,13 +1239,13 @@ void launch_green_forward(xfft_problem *p, Work<T> &w, const Tables<T> &tb, T *f
         xfft_prof_mark(p, -1, s);
         if (ztmpl_size(g.n2)) {
             switch (g.n2) {
-                case 16: zpass<T, 16>(p, A, nrhs, s, tb, w.spec, sz, sy); break;
-                case 32: zpass<T, 32>(p, A, nrhs, s, tb, w.spec, sz, sy); break;
-                case 48: zpass<T, 48>(p, A, nrhs, s, tb, w.spec, sz, sy); break;
-                case 64: zpass<T, 64>(p, A, nrhs, s, tb, w.spec, sz, sy); break;
-                case 96: zpass<T, 96>(p, A, nrhs, s, tb, w.spec, sz, sy); break;
-                case 128: zpass<T, 128>(p, A, nrhs, s, tb, w.spec, sz, sy); break;
-                default: zpass<T, 256>(p, A, nrhs, s, tb, w.spec, sz, sy); break;
+                case 16: zpass<T, 16>(p, A, nrhs, s, tb, w.spec, sz, sy, E); break;
+                case 32: zpass<T, 32>(p, A, nrhs, s, tb, w.spec, sz, sy, E); break;
+                case 48: zpass<T, 48>(p, A, nrhs, s, tb, w.spec, sz, sy, E); break;
+                case 64: zpass<T, 64>(p, A, nrhs, s, tb, w.spec, sz, sy, E); break;
+                case 96: zpass<T, 96>(p, A, nrhs, s, tb, w.spec, sz, sy, E); break;
+                case 128: zpass<T, 128>(p, A, nrhs, s, tb, w.spec, sz, sy, E); break;
+                default: zpass<T, 256>(p, A, nrhs, s, tb, w.spec, sz, sy, E); break;
             }
         } else {
             const int tk = tk_z(g);
@@ -1237,6 +1254,8 @@ void launch_green_forward(xfft_problem *p, Work<T> &w, const Tables<T> &tb, T *f
                                                      w.spec, tk, sz, sy);
         }
         xfft_prof_mark(p, K_FFT_Z_GREEN + (sizeof(T) == 8 ? K_COUNT : 0), s);
+        // the generic z pass has no enriched workgroups
+        if (!ztmpl_size(g.n2) && E.nblk) launch_enr_update<T>(p, w, enr_mode, enr_out, nrhs, flags, parity, s);
     }
     if (!plane) {
         const int tk = tk_for<T>(g.n1, 1, 256);
@@ -1251,19 +1270,21 @@ void launch_green_forward(xfft_problem *p, Work<T> &w, const Tables<T> &tb, T *f
 
 template <typename T>
 void launch_green_inverse(xfft_problem *p, Work<T> &w, const Tables<T> &tb, int mode, T *out, int nrhs,
-                          const Flags *flags, int parity, hipStream_t s) {
+                          const Flags *flags, int parity, hipStream_t s, int enr_mode) {
     const Geometry &g = p->g;
     FftArgs A = fft_args<T>(p, flags, parity);
+    EnrFin<T> E = enr_final_args<T>(p, w, g.nX ? enr_mode : 0);
     xfft_prof_mark(p, -1, s);
     if (plane_path<T>(g)) {
         switch (g.n0) {
-            case 16: plane_inv<T, 16>(p, A, nrhs, s, tb.tws[0], w.spec, mode, out, w.u, w.d); break;
-            case 32: plane_inv<T, 32>(p, A, nrhs, s, tb.tws[0], w.spec, mode, out, w.u, w.d); break;
-            case 48: plane_inv<T, 48>(p, A, nrhs, s, tb.tws[0], w.spec, mode, out, w.u, w.d); break;
-            case 64: plane_inv<T, 64>(p, A, nrhs, s, tb.tws[0], w.spec, mode, out, w.u, w.d); break;
-            case 96: plane_inv<T, 96>(p, A, nrhs, s, tb.tws[0], w.spec, mode, out, w.u, w.d); break;
-            default: plane_inv<T, 128>(p, A, nrhs, s, tb.tws[0], w.spec, mode, out, w.u, w.d); break;
+            case 16: plane_inv<T, 16>(p, A, nrhs, s, tb.tws[0], w.spec, mode, out, w.u, w.d, E); break;
+            case 32: plane_inv<T, 32>(p, A, nrhs, s, tb.tws[0], w.spec, mode, out, w.u, w.d, E); break;
+            case 48: plane_inv<T, 48>(p, A, nrhs, s, tb.tws[0], w.spec, mode, out, w.u, w.d, E); break;
+            case 64: plane_inv<T, 64>(p, A, nrhs, s, tb.tws[0], w.spec, mode, out, w.u, w.d, E); break;
+            case 96: plane_inv<T, 96>(p, A, nrhs, s, tb.tws[0], w.spec, mode, out, w.u, w.d, E); break;
+            default: plane_inv<T, 128>(p, A, nrhs, s, tb.tws[0], w.spec, mode, out, w.u, w.d, E); break;
         }
+        E.mode = 0;
     } else {
         const int pp = pairs_for<T>(g.n0);
         const int64_t npairs = (int64_t)3 * g.n2 * g.n1 / 2;
@@ -1273,15 +1294,16 @@ void launch_green_inverse(xfft_problem *p, Work<T> &w, const Tables<T> &tb, int 
             k_fft_x_inv<T><<<grid, 256, lds, s>>>(A, p->plan[0], tb.tw[0], w.spec, mode, out, w.u, w.d, pp);
     }
     xfft_prof_mark(p, K_FFT_X_INV + (sizeof(T) == 8 ? K_COUNT : 0), s);
+    if (E.mode) launch_enr_final<T>(p, w, E.mode, nrhs, flags, parity, s);
 }
 
 template void launch_green_forward<double>(xfft_problem *, Work<double> &, const Tables<double> &, double *,
-                                           const double *, int, const Flags *, int, hipStream_t);
+                                           const double *, int, const Flags *, int, hipStream_t, int, double *);
 template void launch_green_forward<float>(xfft_problem *, Work<float> &, const Tables<float> &, float *,
-                                          const float *, int, const Flags *, int, hipStream_t);
+                                          const float *, int, const Flags *, int, hipStream_t, int, float *);
 template void launch_green_inverse<double>(xfft_problem *, Work<double> &, const Tables<double> &, int, double *,
-                                           int, const Flags *, int, hipStream_t);
+                                           int, const Flags *, int, hipStream_t, int);
 template void launch_green_inverse<float>(xfft_problem *, Work<float> &, const Tables<float> &, int, float *, int,
-                                          const Flags *, int, hipStream_t);
+                                          const Flags *, int, hipStream_t, int);
 
 }  // namespace xfft

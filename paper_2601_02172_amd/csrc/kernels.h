@@ -21,16 +21,21 @@ void launch_operator(xfft_problem *p, Work<T> &w, const Tables<T> &tb, const T *
                      hipStream_t s, bool stress = true);
 
 // Green operator passes.  mode_x_fwd: the residual update f -= alpha z is fused
-// when z is non-null.  The z pass writes the Parseval partials.
+// when z is non-null.  The z pass writes the Parseval partials.  The enriched
+// residual update of launch_enr_update (mode enr_mode, output enr_out) follows
+// at the same point: as extra workgroups of the compile-time z pass, else as a
+// kernel of its own.
 template <typename T>
 void launch_green_forward(xfft_problem *p, Work<T> &w, const Tables<T> &tb, T *f, const T *z, int nrhs,
-                          const Flags *flags, int parity, hipStream_t s);
+                          const Flags *flags, int parity, hipStream_t s, int enr_mode, T *enr_out);
 
 // mode 0: out = P^-1 f (FE part) written to `out`; mode 1: CG update
-// (u += alpha d_old, d = y + beta d_old); mode 2: d = y.
+// (u += alpha d_old, d = y + beta d_old); mode 2: d = y.  The enriched update
+// of launch_enr_final (enr_mode 1 or 2; 0: none) runs inside the xy-plane
+// kernels when they are used, else as a kernel of its own.
 template <typename T>
 void launch_green_inverse(xfft_problem *p, Work<T> &w, const Tables<T> &tb, int mode, T *out, int nrhs,
-                          const Flags *flags, int parity, hipStream_t s);
+                          const Flags *flags, int parity, hipStream_t s, int enr_mode);
 
 // Enriched block: mode 0 residual partial only (out = f~ written when out non-null);
 // mode 1: f~ -= alpha z~ then partial.
@@ -41,6 +46,11 @@ void launch_enr_update(xfft_problem *p, Work<T> &w, int mode, T *out, int nrhs, 
 template <typename T>
 void launch_enr_final(xfft_problem *p, Work<T> &w, int mode, int nrhs, const Flags *flags, int parity,
                       hipStream_t s);
+// kernel arguments of the two enriched updates (enriched.h)
+template <typename T> struct EnrUpd;
+template <typename T> struct EnrFin;
+template <typename T> EnrUpd<T> enr_update_args(xfft_problem *p, Work<T> &w, int mode, T *out);
+template <typename T> EnrFin<T> enr_final_args(xfft_problem *p, Work<T> &w, int mode);
 
 // Scalar recurrences (one block per right-hand side).
 enum ScalarOp { SC_INIT_SIGMA = 0, SC_INIT_RES = 1, SC_ALPHA = 2, SC_BETA = 3, SC_SUM_ONLY = 4, SC_SUM_GREEN = 5 };

@@ -273,6 +273,19 @@ __global__ __launch_bounds__(256) void k_regular(OpArgs<T> A) {
     mv[0] = elem(A.vmat, colv + plane_off(k0 - 1));
     mv[1] = (k0 < k1) ? elem(A.vmat, colv + plane_off(k0)) : 0;
     mv[2] = 0;
+    // buffered corner forces of an irregular voxel: in FP32 those of the voxel
+    // one layer ahead are loaded a layer before they are used (24 more
+    // registers, which FP64 cannot spare), so their latency is hidden
+    constexpr bool PF = sizeof(T) == 4;
+    T Fn[8][3];
+    auto fetch_cut = [&](int mq) {
+        const uint32_t cq = (uint32_t)(-mq - 1) * 24u;
+#pragma unroll
+        for (int c = 0; c < 8; ++c)
+#pragma unroll
+            for (int i = 0; i < 3; ++i) Fn[c][i] = elem(cutbuf, cq + 3 * c + i);
+    };
+    if (PF && mv[0] < 0) fetch_cut(mv[0]);
     __syncthreads();
 
     T acc[3] = {0, 0, 0};
@@ -284,18 +297,17 @@ __global__ __launch_bounds__(256) void k_regular(OpArgs<T> A) {
         const bool more = kl + 2 <= k1, more2 = kl + 3 <= k1;
         if (more2) fetch_plane(kl + 3, R[sb]);
         mv[sn] = (kl + 2 < k1) ? elem(A.vmat, colv + plane_off(kl + 2)) : 0;
-        const int m = mv[sb];
+        const int m = mv[sb], mn = mv[st];
         const uint32_t vox = colv + plane_off(kl);
         T F[8][3];
         if (m < 0) {
-            // buffered corner forces of an irregular voxel: the loads are issued
-            // before the regular lanes compute, so their latency is overlapped
-            const uint32_t cq = (uint32_t)(-m - 1) * 24u;
+            if (!PF) fetch_cut(m);
 #pragma unroll
             for (int c = 0; c < 8; ++c)
 #pragma unroll
-                for (int i = 0; i < 3; ++i) F[c][i] = elem(cutbuf, cq + 3 * c + i);
+                for (int i = 0; i < 3; ++i) F[c][i] = Fn[c][i];
         }
+        if (PF && mn < 0) fetch_cut(mn);
         if (m >= 0) {
             T U[8][3];
 #pragma unroll
