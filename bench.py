@@ -69,17 +69,19 @@ def algorithmic_bytes(g, s, nrhs):
     specN = g["n2"] * g["n1"] * nh               # complex entries per component
     spec = 3 * specN * 2 * s                     # one 3-component half spectrum
     field = 3 * N * s                            # one 3-component nodal field
+    gather = nX * (8 * 4 + 3 * s)                # enriched gather: source ids, write z~
     per = {
-        "regular_voxels": 2 * field + 4 * N,                      # read d, write z, read material ids
+        # read d, write z, read material ids; the launch also runs the enriched gather
+        "regular_voxels": 2 * field + 4 * N + gather,
         # u, level set, enriched ids, labels, scaled enriched d, corner forces; moments per cut element
         "irregular_voxels": nirr * (8 * 3 * s + 8 * s + 8 * 4 + 12 * 4 + 8 * 3 * s + 48 * s)
                             + g.get("n_cut_elements", 0) * 12 * s,
-        "enriched_gather": nX * (8 * 4 + 3 * s),
+        "enriched_gather": gather,
         "fft_x_forward": 3 * field + spec,                        # read f, z; write f, spectrum
         "fft_y_forward": 2 * spec,
-        "fft_z_green": 2 * spec,
+        "fft_z_green": 2 * spec + nX * 3 * s * 3,                 # + enriched residual update
         "fft_y_inverse": 2 * spec,
-        "fft_x_inverse": spec + 4 * field,                        # read spectrum, d, u; write d, u
+        "fft_x_inverse": spec + 4 * field + nX * 3 * s * 5,       # read spectrum, d, u; write d, u; + enriched
         "enriched_residual": nX * 3 * s * 3,
         "enriched_update": nX * 3 * s * 5,
         "scalars": 0,

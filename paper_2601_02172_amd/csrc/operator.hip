@@ -1,6 +1,6 @@
 // Matrix-free scaled X-FEM operator (eqs. linearSystem_element, resVector).
 //
-// Three kernels per application, all deterministic (no atomics):
+// Two kernels per application, all deterministic (no atomics):
 //  k_irregular  one thread per irregular voxel (a voxel with a cut element or
 //               elements of different materials); evaluates its six elements
 //               (cut ones by the per-side moment form of element.h) and writes
@@ -9,8 +9,9 @@
 //               column of voxels, evaluates the six Kuhn elements of one voxel
 //               per plane (or takes the buffered corner forces of an irregular
 //               voxel) and the corner forces are summed per node through LDS;
-//  k_enriched   one thread per enriched node; sums the buffered enriched
-//               corner forces of its (at most eight) irregular voxels.
+//  enriched     one thread per enriched node; sums the buffered enriched
+//               corner forces of its (at most eight) irregular voxels (extra
+//               workgroups at the end of the k_regular launch).
 #include "kernels.h"
 #include <type_traits>
 #include "element.h"
@@ -51,6 +52,8 @@ struct OpArgs {
     int64_t N, nX, nirr;
     int kz, tiles_x;
     int tiles_xy, reg_blocks, cut_blocks, enr_blocks;   // workgroups per right-hand side
+    int nrhs;                 // right-hand sides of the launch
+    int enr_slot0;            // first partial slot of the enriched gather
 };
 
 template <typename T>
@@ -189,8 +192,16 @@ __global__ __launch_bounds__(256) void k_regular(OpArgs<T> A) {
     __shared__ T FB[3][6][TE * TE];    // row sums for the node above, one buffer per layer of the unrolled march
     __shared__ double red[4 * 7];
 
+    // workgroups after the regular ones gather the enriched forces (they only
+    // need the irregular-voxel buffer, so they fill the tail of this launch)
+    const int64_t nreg = (int64_t)A.reg_blocks * A.nrhs;
+    if ((int64_t)blockIdx.x >= nreg) {
+        const int e = (int)(blockIdx.x - nreg), re = e / A.enr_blocks;
+        if (rhs_active(A, re)) enriched_block<T, HX>(A, re, e - re * A.enr_blocks, red);
+        return;
+    }
     // logical block: (rhs, z chunk, tile y, tile x), x fastest
-    const int64_t lb = xcd_remap(blockIdx.x, gridDim.x);
+    const int64_t lb = xcd_remap(blockIdx.x, nreg);
     const int r = (int)(lb / A.reg_blocks), blk = (int)(lb % A.reg_blocks);
     if (!rhs_active(A, r)) return;
     const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
@@ -563,12 +574,9 @@ __global__ __launch_bounds__(128) void k_irregular(OpArgs<T> A) {
 }
 
 // ---------------------------------------------------------------- enriched gather
+// Workgroup blk (256 threads) of load r: one enriched node per thread.
 template <typename T, bool HX>
-__global__ __launch_bounds__(256) void k_enriched(OpArgs<T> A) {
-    __shared__ double red[4 * 7];
-    const int64_t lb = xcd_remap(blockIdx.x, gridDim.x);
-    const int r = (int)(lb / A.enr_blocks), blk = (int)(lb % A.enr_blocks);
-    if (!rhs_active(A, r)) return;
+__device__ __forceinline__ void enriched_block(const OpArgs<T> &A, int r, int blk, double *red) {
     const int64_t jn = (int64_t)blk * blockDim.x + threadIdx.x;
     double acc7[7] = {0, 0, 0, 0, 0, 0, 0};
     if (jn < A.nX) {
@@ -599,7 +607,7 @@ __global__ __launch_bounds__(256) void k_enriched(OpArgs<T> A) {
     }
     block_sum<7>(acc7, red);
     if (threadIdx.x == 0) {
-        double *P = A.partial + ((int64_t)r * A.nslots + A.slot0 + blk) * NPART;
+        double *P = A.partial + ((int64_t)r * A.nslots + A.enr_slot0 + blk) * NPART;
 #pragma unroll
         for (int q = 0; q < 7; ++q) P[q] = acc7[q];
     }
@@ -625,6 +633,8 @@ void launch_operator(xfft_problem *p, Work<T> &w, const Tables<T> &tb, const T *
     A.kz = L.kz; A.tiles_x = L.tiles_x;
     A.tiles_xy = L.tiles_x * L.tiles_y; A.reg_blocks = L.tiles_x * L.tiles_y * L.zchunks; A.cut_blocks = L.cut_n;
     A.enr_blocks = L.enr_n;
+    A.nrhs = nrhs;
+    A.enr_slot0 = L.enr0;
     const bool hx = x != nullptr;
     if (g.nirr > 0) {
         A.slot0 = L.cut0;
@@ -638,7 +648,8 @@ void launch_operator(xfft_problem *p, Work<T> &w, const Tables<T> &tb, const T *
     }
     {
         A.slot0 = L.fe0;
-        dim3 grid((unsigned)(L.tiles_x * L.tiles_y * L.zchunks) * nrhs, 1);
+        if (g.nX == 0) A.enr_blocks = 0;
+        dim3 grid((unsigned)(L.tiles_x * L.tiles_y * L.zchunks + A.enr_blocks) * nrhs, 1);
         xfft_prof_mark(p, -1, s);
         if (hx && use_ebar) k_regular<T, true, true, true><<<grid, 256, 0, s>>>(A);
         else if (hx && stress) k_regular<T, true, false, true><<<grid, 256, 0, s>>>(A);
@@ -646,14 +657,6 @@ void launch_operator(xfft_problem *p, Work<T> &w, const Tables<T> &tb, const T *
         else if (use_ebar) k_regular<T, false, true, true><<<grid, 256, 0, s>>>(A);
         else k_regular<T, false, false, false><<<grid, 256, 0, s>>>(A);
         xfft_prof_mark(p, K_REGULAR + (sizeof(T) == 8 ? K_COUNT : 0), s);
-    }
-    if (g.nX > 0) {
-        A.slot0 = L.enr0;
-        dim3 grid((unsigned)L.enr_n * nrhs, 1);
-        xfft_prof_mark(p, -1, s);
-        if (hx) k_enriched<T, true><<<grid, 256, 0, s>>>(A);
-        else k_enriched<T, false><<<grid, 256, 0, s>>>(A);
-        xfft_prof_mark(p, K_ENRICHED + (sizeof(T) == 8 ? K_COUNT : 0), s);
     }
 }
 
