@@ -98,7 +98,7 @@ void xfft_default_options(xfft_options *opt);
  * largest L, side L < 0 that of its vertex with the largest |L| (ties: first
  * vertex along the Kuhn path).  On success *out owns device memory until
  * xfft_destroy.  Size limits (32-bit byte offsets inside one load's fields):
- * 24 N < 2^32 and 192 x (irregular voxels) < 2^32, else EINVAL.
+ * 24 N < 2^32 and 384 x (irregular voxels) < 2^32, else EINVAL.
  * Errors: EINVAL, ENOMEM, EDEVICE (nothing is allocated then). */
 int xfft_setup(const int32_t n[3], const double len[3], const double *levelset,
                const int32_t *phase, int32_t nphase, const double *lame,

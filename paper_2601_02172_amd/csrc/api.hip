@@ -59,7 +59,7 @@ template <typename T> int alloc_work(xfft_problem *p, Work<T> &w, int cap) {
     const Geometry &g = p->g;
     const size_t nf = (size_t)cap * 3 * g.N, ne = (size_t)cap * 3 * (g.nX > 0 ? g.nX : 1);
     const size_t ns = (size_t)cap * 3 * g.n2 * g.n1 * g.nh;
-    const size_t nc = (size_t)cap * (g.nirr > 0 ? g.nirr : 1) * 48;
+    const size_t nc = (size_t)cap * (size_t)cut_rows(g.nirr > 0 ? g.nirr : 1) * 48;
     T **fe_ptrs[] = {&w.u, &w.f, &w.d, &w.z};
     for (T **q : fe_ptrs)
         if (hipMalloc(q, nf * sizeof(T)) != hipSuccess) return XFFT_ENOMEM;
@@ -700,8 +700,8 @@ int xfft_setup(const int32_t n[3], const double len[3], const double *levelset, 
         rc = XFFT_EDEVICE;
     if (!rc) rc = run_setup(p, Lraw);
     if (Lraw) (void)hipFree(Lraw);
-    // and the corner-force buffer of one load (24 values per irregular voxel) likewise
-    if (!rc && g.nirr * 24 * (int64_t)sizeof(double) >= ((int64_t)1 << 32)) rc = XFFT_EINVAL;
+    // and the corner-force buffer of one load (48 values per irregular voxel) likewise
+    if (!rc && cut_rows(g.nirr) * 48 * (int64_t)sizeof(double) >= ((int64_t)1 << 32)) rc = XFFT_EINVAL;
     if (!rc) rc = compute_tables(p);
     if (!rc) {
         for (int a = 0; a < 3; ++a)

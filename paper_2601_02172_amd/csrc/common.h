@@ -109,8 +109,10 @@ struct Geometry {
 template <typename T> struct Tables {
     T *lame = nullptr;       // [nphase][2]
     T *d0is = nullptr;       // [nX] D0^-1/2
-    T *irr_L = nullptr;      // [nirr][8] snapped corner level set of irregular voxels
-    // [nirr][6][12] moments of the smaller side of each cut Kuhn tet of the
+    // Tables of the irregular voxels are stored with the voxel index fastest
+    // ([row][nirr]), so that the lanes of a wave access consecutive words.
+    T *irr_L = nullptr;      // [8][nirr] snapped corner level set of irregular voxels
+    // [6][10][nirr] moments of the smaller side of each cut Kuhn tet of the
     // irregular voxels (upper triangle; the sign bit of entry 0 marks the - side),
     // computed in FP64 and rounded once
     T *irr_M = nullptr;
@@ -125,8 +127,14 @@ template <typename T> struct Work {
     T *u = nullptr, *f = nullptr, *d = nullptr, *z = nullptr;          // [cap][3][N]
     T *ue = nullptr, *fe = nullptr, *de = nullptr, *ze = nullptr;      // [cap][3][nX]
     cpx<T> *spec = nullptr;                                            // [cap][3][n2][n1][nh]
-    T *cutbuf = nullptr;     // [cap][2][nirr][8][3]: FE, then scaled enriched corner forces
+    // [cap][2][cut_rows(nirr) / 64][6][64][4]: FE, then scaled enriched corner
+    // forces of the irregular voxels, 24 values (corner-major, xyz) per voxel in
+    // groups of 64 voxels, four values per row (see cut_index in operator.hip)
+    T *cutbuf = nullptr;
 };
+
+// irregular voxels rounded up to whole groups of 64 (corner-force buffer)
+__host__ __device__ inline int64_t cut_rows(int64_t nirr) { return (nirr + 63) & ~(int64_t)63; }
 
 // Partial-sum slot layout per right-hand side.
 struct SlotLayout {
@@ -185,8 +193,8 @@ struct xfft_problem {
     int32_t *phase = nullptr;      // [N]
     int32_t *vmat = nullptr;       // [N] material (>= 0) or -(irregular index + 1)
     int32_t *irr = nullptr;        // [nirr] voxel of each irregular voxel
-    int32_t *irr_j = nullptr;      // [nirr][8] enriched index per corner or -1
-    int32_t *irr_lab = nullptr;    // [nirr][6][2] element labels: uncut (both) or (+ side, - side)
+    int32_t *irr_j = nullptr;      // [8][nirr] enriched index per corner or -1
+    int32_t *irr_lab = nullptr;    // [6][2][nirr] element labels: uncut (both) or (+ side, - side)
     int32_t *jlist = nullptr;      // [nX]
     int32_t *enr_src = nullptr;    // [nX][8] 8 * irregular voxel + corner feeding enriched node j, or -1
     double *d0 = nullptr;          // [nX]

@@ -244,8 +244,8 @@ __global__ __launch_bounds__(64) void k_grad_irregular(GradArgs A) {
         for (int c = 0; c < 8; ++c) {
             const int64_t node = wrapg(i + (c & 1), A.n0) +
                                  (int64_t)A.n0 * (wrapg(j + ((c >> 1) & 1), A.n1) + (int64_t)A.n1 * wrapg(k + (c >> 2), A.n2));
-            Lc[c] = A.irr_L[qv * 8 + c];
-            const int jc = A.irr_j[qv * 8 + c];
+            Lc[c] = A.irr_L[c * A.nirr + qv];
+            const int jc = A.irr_j[c * A.nirr + qv];
             const double sc = jc >= 0 ? A.d0is[jc] : 0.0;
 #pragma unroll
             for (int l = 0; l < 6; ++l)
@@ -255,7 +255,10 @@ __global__ __launch_bounds__(64) void k_grad_irregular(GradArgs A) {
                     Q[l][c][d] = jc >= 0 ? sc * A.ue[((int64_t)l * 3 + d) * A.nX + jc] : 0.0;
                 }
         }
-        const int32_t *lab = A.irr_lab + qv * 12;
+        // element labels of this voxel (rows nirr apart)
+        int32_t lab[12];
+#pragma unroll
+        for (int q = 0; q < 12; ++q) lab[q] = A.irr_lab[q * A.nirr + qv];
         irregular_tet_grad<0>(Lc, lab, U, Q, tab, A.nphase);
         irregular_tet_grad<1>(Lc, lab, U, Q, tab, A.nphase);
         irregular_tet_grad<2>(Lc, lab, U, Q, tab, A.nphase);

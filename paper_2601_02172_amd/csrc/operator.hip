@@ -26,6 +26,15 @@ constexpr int TC = TE + 1;      // node columns per tile edge (halo on the + sid
 
 __device__ __forceinline__ int wrapi(int a, int n) { return a < 0 ? a + n : (a >= n ? a - n : a); }
 
+// Position of value k (0..23: corner k / 3, component k % 3) of irregular voxel q
+// in one half of the corner-force buffer: groups of 64 voxels, six rows of four
+// values per voxel, rows of the 64 voxels adjacent.  The irregular kernel writes
+// a whole row per lane and a wave covers a contiguous block; the regular kernel
+// reads a voxel's 24 values as six 4-vectors.
+__device__ __forceinline__ uint32_t cut_index(uint32_t q, int k) {
+    return (((q >> 6) * 6 + (uint32_t)(k >> 2)) * 64 + (q & 63)) * 4 + (uint32_t)(k & 3);
+}
+
 // base[i] with a 32-bit byte offset (uniform base pointer + 32-bit lane offset)
 template <typename P> __device__ __forceinline__ P &elem(P *base, uint32_t i) {
     using B = typename std::conditional<std::is_const<P>::value, const char, char>::type;
@@ -42,8 +51,8 @@ struct OpArgs {
     int parity;
     const int32_t *vmat, *irr, *irr_j, *irr_lab, *jlist, *enr_src;
     const T *d0is, *lame;
-    const T *irr_L;           // [nirr][8] corner level set
-    const T *irr_M;           // [nirr][6][12] precomputed moments of the directly built side
+    const T *irr_L;           // [8][nirr] corner level set
+    const T *irr_M;           // [6][10][nirr] precomputed moments of the smaller side
     T *cutbuf;
     double *partial;
     int nslots, slot0;
@@ -230,7 +239,7 @@ __global__ __launch_bounds__(256) void k_regular(OpArgs<T> A) {
 
     const T *x = HX ? A.x + (int64_t)r * 3 * N : nullptr;
     T *y = A.y + (int64_t)r * 3 * N;
-    const T *cutbuf = A.cutbuf + (int64_t)r * A.nirr * 48;
+    const T *cutbuf = A.cutbuf + (int64_t)r * cut_rows(A.nirr) * 48;
     T eb[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
     if constexpr (EB) {
         const Sym<T> e = load_ebar<T>(A.ebar + 6 * r);
@@ -290,11 +299,18 @@ __global__ __launch_bounds__(256) void k_regular(OpArgs<T> A) {
     constexpr bool PF = sizeof(T) == 4;
     T Fn[8][3];
     auto fetch_cut = [&](int mq) {
-        const uint32_t cq = (uint32_t)(-mq - 1) * 24u;
+        const uint32_t q = (uint32_t)(-mq - 1);
+        T v[24];
+#pragma unroll
+        for (int k4 = 0; k4 < 6; ++k4) {
+            using V4 = typename std::conditional<sizeof(T) == 4, float4, double4>::type;
+            const V4 w = elem(reinterpret_cast<const V4 *>(cutbuf), cut_index(q, 4 * k4) >> 2);
+            v[4 * k4] = w.x; v[4 * k4 + 1] = w.y; v[4 * k4 + 2] = w.z; v[4 * k4 + 3] = w.w;
+        }
 #pragma unroll
         for (int c = 0; c < 8; ++c)
 #pragma unroll
-            for (int i = 0; i < 3; ++i) Fn[c][i] = elem(cutbuf, cq + 3 * c + i);
+            for (int i = 0; i < 3; ++i) Fn[c][i] = v[3 * c + i];
     };
     if (PF && mv[0] < 0) fetch_cut(mv[0]);
     __syncthreads();
@@ -394,8 +410,9 @@ __global__ __launch_bounds__(256) void k_regular(OpArgs<T> A) {
 }
 
 // ---------------------------------------------------------------- irregular voxel
+// M, lab: moment and label tables (rows nirr apart, irregular voxel qv fastest).
 template <int t, typename T, bool EB>
-__device__ __forceinline__ void irregular_tet(const T (&Lc)[8], const T *__restrict__ Mq, int64_t nirr,
+__device__ __forceinline__ void irregular_tet(const T (&Lc)[8], const T *__restrict__ M, int64_t nirr, uint32_t qv,
                                               const T (&U)[8][3], const T (&Q)[8][3],
                                               const int32_t *lab, const T *lame, const Sym<T> &eb,
                                               T (&F)[8][3], T (&Fe)[8][3], Sym<T> &S) {
@@ -412,7 +429,7 @@ __device__ __forceinline__ void irregular_tet(const T (&Lc)[8], const T *__restr
     const T V = (T)(1.0 / 6.0);
     const Grad<T> HF = kuhn_grad<t>(u);
     if (!(anyp && anyn)) {
-        const int m = lab[2 * t];
+        const int m = elem(lab + (2 * t) * nirr, qv);
         Sym<T> e = sym_of(HF);
         if constexpr (EB) {
             e.xx += eb.xx; e.yy += eb.yy; e.zz += eb.zz; e.yz += eb.yz; e.xz += eb.xz; e.xy += eb.xy;
@@ -427,22 +444,9 @@ __device__ __forceinline__ void irregular_tet(const T (&Lc)[8], const T *__restr
     // the larger side is its complement.
     T Mp[4][4], Mm[4][4];
     {
-        T ms[12];
-        if constexpr (sizeof(T) == 4) {
-            const float4 *m4 = reinterpret_cast<const float4 *>(Mq + 12 * t);
+        T ms[10];
 #pragma unroll
-            for (int e = 0; e < 3; ++e) {
-                const float4 w = m4[e];
-                ms[4 * e] = w.x; ms[4 * e + 1] = w.y; ms[4 * e + 2] = w.z; ms[4 * e + 3] = w.w;
-            }
-        } else {
-            const double2 *m2 = reinterpret_cast<const double2 *>(Mq + 12 * t);
-#pragma unroll
-            for (int e = 0; e < 5; ++e) {
-                const double2 w = m2[e];
-                ms[2 * e] = w.x; ms[2 * e + 1] = w.y;
-            }
-        }
+        for (int e = 0; e < 10; ++e) ms[e] = elem(M + (t * 10 + e) * nirr, qv);
         const bool pos = !signbit(ms[0]);
         ms[0] = fabs(ms[0]);
         T Ms[4][4];
@@ -457,7 +461,7 @@ __device__ __forceinline__ void irregular_tet(const T (&Lc)[8], const T *__restr
 #pragma unroll
     for (int side = 0; side < 2; ++side) {
         const T sg = side == 0 ? (T)1 : (T)-1;
-        const int m = lab[2 * t + side];
+        const int m = elem(lab + (2 * t + side) * nirr, qv);
         const T lam = lame[2 * m], mu2 = (T)2 * lame[2 * m + 1];
         T w[4];
 #pragma unroll
@@ -513,6 +517,7 @@ __global__ __launch_bounds__(128) void k_irregular(OpArgs<T> A) {
     const int r = (int)(lb / A.cut_blocks), blk = (int)(lb % A.cut_blocks);
     if (!rhs_active(A, r)) return;
     const int64_t qv = (int64_t)blk * blockDim.x + threadIdx.x;
+    const uint32_t q32 = (uint32_t)qv;
     double acc7[7] = {0, 0, 0, 0, 0, 0, 0};
     if (qv < A.nirr) {
         const int64_t N = A.N;
@@ -526,8 +531,8 @@ __global__ __launch_bounds__(128) void k_irregular(OpArgs<T> A) {
         for (int c = 0; c < 8; ++c) {
             const int64_t node = wrapi(i + (c & 1), A.n0) +
                                  (int64_t)A.n0 * (wrapi(j + ((c >> 1) & 1), A.n1) + (int64_t)A.n1 * wrapi(k + (c >> 2), A.n2));
-            Lc[c] = A.irr_L[qv * 8 + c];
-            const int jc = A.irr_j[qv * 8 + c];
+            Lc[c] = elem(A.irr_L + c * A.nirr, q32);
+            const int jc = elem(A.irr_j + c * A.nirr, q32);
             sc[c] = jc >= 0 ? A.d0is[jc] : (T)0;
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
@@ -537,30 +542,36 @@ __global__ __launch_bounds__(128) void k_irregular(OpArgs<T> A) {
         }
         Sym<T> eb = sym_zero<T>();
         if constexpr (EB) eb = load_ebar<T>(A.ebar + 6 * r);
-        const int32_t *lab = A.irr_lab + qv * 12;
+        const int32_t *lab = A.irr_lab;
         T F[8][3], Fe[8][3];
 #pragma unroll
         for (int c = 0; c < 8; ++c)
 #pragma unroll
             for (int d = 0; d < 3; ++d) F[c][d] = Fe[c][d] = (T)0;
         Sym<T> S = sym_zero<T>();
-        irregular_tet<0, T, EB>(Lc, A.irr_M + qv * 72, A.nirr, U, Q, lab, A.lame, eb, F, Fe, S);
-        irregular_tet<1, T, EB>(Lc, A.irr_M + qv * 72, A.nirr, U, Q, lab, A.lame, eb, F, Fe, S);
-        irregular_tet<2, T, EB>(Lc, A.irr_M + qv * 72, A.nirr, U, Q, lab, A.lame, eb, F, Fe, S);
-        irregular_tet<3, T, EB>(Lc, A.irr_M + qv * 72, A.nirr, U, Q, lab, A.lame, eb, F, Fe, S);
-        irregular_tet<4, T, EB>(Lc, A.irr_M + qv * 72, A.nirr, U, Q, lab, A.lame, eb, F, Fe, S);
-        irregular_tet<5, T, EB>(Lc, A.irr_M + qv * 72, A.nirr, U, Q, lab, A.lame, eb, F, Fe, S);
-        // per-load buffer: FE corner forces [nirr][8][3], then scaled enriched ones [nirr][8][3]
-        T *cb = A.cutbuf + (int64_t)r * A.nirr * 48 + qv * 24;
-        T *cbe = cb + A.nirr * 24;
+        irregular_tet<0, T, EB>(Lc, A.irr_M, A.nirr, q32, U, Q, lab, A.lame, eb, F, Fe, S);
+        irregular_tet<1, T, EB>(Lc, A.irr_M, A.nirr, q32, U, Q, lab, A.lame, eb, F, Fe, S);
+        irregular_tet<2, T, EB>(Lc, A.irr_M, A.nirr, q32, U, Q, lab, A.lame, eb, F, Fe, S);
+        irregular_tet<3, T, EB>(Lc, A.irr_M, A.nirr, q32, U, Q, lab, A.lame, eb, F, Fe, S);
+        irregular_tet<4, T, EB>(Lc, A.irr_M, A.nirr, q32, U, Q, lab, A.lame, eb, F, Fe, S);
+        irregular_tet<5, T, EB>(Lc, A.irr_M, A.nirr, q32, U, Q, lab, A.lame, eb, F, Fe, S);
+        // per-load buffer: FE corner forces [8][3][nirr], then scaled enriched ones [8][3][nirr]
+        T *cb = A.cutbuf + (int64_t)r * cut_rows(A.nirr) * 48;
+        T *cbe = cb + cut_rows(A.nirr) * 24;
+        T vf[24], ve[24];
 #pragma unroll
-        for (int c = 0; c < 8; ++c) {
-            cb[3 * c + 0] = F[c][0];
-            cb[3 * c + 1] = F[c][1];
-            cb[3 * c + 2] = F[c][2];
-            cbe[3 * c + 0] = sc[c] * Fe[c][0];
-            cbe[3 * c + 1] = sc[c] * Fe[c][1];
-            cbe[3 * c + 2] = sc[c] * Fe[c][2];
+        for (int c = 0; c < 8; ++c)
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                vf[3 * c + i] = F[c][i];
+                ve[3 * c + i] = sc[c] * Fe[c][i];
+            }
+        using V4 = typename std::conditional<sizeof(T) == 4, float4, double4>::type;
+#pragma unroll
+        for (int k4 = 0; k4 < 6; ++k4) {
+            const uint32_t o = cut_index(q32, 4 * k4) >> 2;
+            elem(reinterpret_cast<V4 *>(cb), o) = V4{vf[4 * k4], vf[4 * k4 + 1], vf[4 * k4 + 2], vf[4 * k4 + 3]};
+            elem(reinterpret_cast<V4 *>(cbe), o) = V4{ve[4 * k4], ve[4 * k4 + 1], ve[4 * k4 + 2], ve[4 * k4 + 3]};
         }
         add_sym(acc7, S);
         if (A.vstress) store_vstress(A.vstress + (int64_t)r * 6 * N, N, vox, S);
@@ -585,13 +596,15 @@ __device__ __forceinline__ void enriched_block(const OpArgs<T> &A, int r, int bl
         const int4 s0 = reinterpret_cast<const int4 *>(A.enr_src)[2 * jn];
         const int4 s1 = reinterpret_cast<const int4 *>(A.enr_src)[2 * jn + 1];
         const int src[8] = {s0.x, s0.y, s0.z, s0.w, s1.x, s1.y, s1.z, s1.w};
-        const T *cbe = A.cutbuf + (int64_t)r * A.nirr * 48 + A.nirr * 24;
+        const T *cbe = A.cutbuf + (int64_t)r * cut_rows(A.nirr) * 48 + cut_rows(A.nirr) * 24;
         T s[3] = {0, 0, 0};
 #pragma unroll
         for (int c = 0; c < 8; ++c) {
             if (src[c] >= 0) {
-                const T *cb = cbe + (int64_t)src[c] * 3;
-                s[0] += cb[0]; s[1] += cb[1]; s[2] += cb[2];
+                const uint32_t q = (uint32_t)(src[c] >> 3);
+                const int k = 3 * (src[c] & 7);
+#pragma unroll
+                for (int i = 0; i < 3; ++i) s[i] += elem(cbe, cut_index(q, k + i));
             }
         }
         T *ye = A.ye + (int64_t)r * 3 * A.nX;

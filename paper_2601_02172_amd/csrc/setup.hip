@@ -171,12 +171,13 @@ __global__ __launch_bounds__(SCAN_T) void k_scan_emit(int64_t n, const uint8_t *
 }
 
 template <int t>
-__device__ __forceinline__ void irr_labels_tet(const double (&Lc)[8], const int (&pc)[8], int32_t *out) {
+__device__ __forceinline__ void irr_labels_tet(const double (&Lc)[8], const int (&pc)[8], int32_t *out,
+                                               int64_t stride) {
     bool cut, ml;
     int lu, lp, ln;
     classify_tet<t>(Lc, pc, cut, lu, lp, ln, ml);
-    out[2 * t] = cut ? lp : lu;
-    out[2 * t + 1] = cut ? ln : lu;
+    out[(2 * t) * stride] = cut ? lp : lu;
+    out[(2 * t + 1) * stride] = cut ? ln : lu;
 }
 
 __global__ void k_irr_tables(int64_t nirr, int n0, int n1, int n2, const int32_t *irr, const double *Ls,
@@ -193,33 +194,34 @@ __global__ void k_irr_tables(int64_t nirr, int n0, int n1, int n2, const int32_t
         const int64_t nd = corner_node(i, j, k, c, n0, n1, n2);
         Lc[c] = Ls[nd];
         pc[c] = phase[nd];
-        irr_j[q * 8 + c] = jmap[nd];
-        irr_L64[q * 8 + c] = Lc[c];
-        irr_L32[q * 8 + c] = (float)Lc[c];
+        irr_j[c * nirr + q] = jmap[nd];
+        irr_L64[c * nirr + q] = Lc[c];
+        irr_L32[c * nirr + q] = (float)Lc[c];
     }
-    int32_t *lab = irr_lab + q * 12;
-    irr_labels_tet<0>(Lc, pc, lab);
-    irr_labels_tet<1>(Lc, pc, lab);
-    irr_labels_tet<2>(Lc, pc, lab);
-    irr_labels_tet<3>(Lc, pc, lab);
-    irr_labels_tet<4>(Lc, pc, lab);
-    irr_labels_tet<5>(Lc, pc, lab);
+    int32_t *lab = irr_lab + q;
+    irr_labels_tet<0>(Lc, pc, lab, nirr);
+    irr_labels_tet<1>(Lc, pc, lab, nirr);
+    irr_labels_tet<2>(Lc, pc, lab, nirr);
+    irr_labels_tet<3>(Lc, pc, lab, nirr);
+    irr_labels_tet<4>(Lc, pc, lab, nirr);
+    irr_labels_tet<5>(Lc, pc, lab, nirr);
 }
 
 // Side moments of the six Kuhn tets of every irregular voxel (exact
 // integration over the two sides of a cut element): geometry only, so they are
 // computed once per setup in FP64 instead of in every operator application.
-// Stored per voxel and tet, 12 values [qv][t][12]: the upper triangle (row by
-// row) of the moments of the side with the smaller volume, whose entry 0
-// carries the sign bit when that side is the - side (all moments are >= 0),
-// then two zeros.  The operator forms the other side as the complement
-// M^tet - Ms, which is accurate in FP32 because it is the larger side.
+// Stored per tet, 10 values [t][e][qv] (irregular voxel fastest, so that the
+// lanes of a wave read consecutive words): the upper triangle (row by row) of
+// the moments of the side with the smaller volume, whose entry 0 carries the
+// sign bit when that side is the - side (all moments are >= 0).  The operator
+// forms the other side as the complement M^tet - Ms, which is accurate in FP32
+// because it is the larger side.
 __global__ void k_irr_moments(int64_t nirr, const double *irr_L64, double *M64, float *M32) {
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= nirr) return;
     double Lc[8];
 #pragma unroll
-    for (int c = 0; c < 8; ++c) Lc[c] = irr_L64[q * 8 + c];
+    for (int c = 0; c < 8; ++c) Lc[c] = irr_L64[c * nirr + q];
     for (int t = 0; t < 6; ++t) {
         double L[4];
         bool anyp = false, anyn = false;
@@ -254,19 +256,17 @@ __global__ void k_irr_moments(int64_t nirr, const double *irr_L64, double *M64, 
 #pragma unroll
                 for (int d = 0; d < 4; ++d) Ms[c][d] = 0.0;
         }
-        double v[12];
+        double v[10];
         int k = 0;
 #pragma unroll
         for (int c = 0; c < 4; ++c)
 #pragma unroll
             for (int d = c; d < 4; ++d, ++k) v[k] = Ms[c][d];
-        v[10] = v[11] = 0.0;
         if (!pos) v[0] = -v[0];                       // sign bit marks the - side (also for +0)
-        const int64_t o = (q * 6 + t) * 12;
 #pragma unroll
-        for (int e = 0; e < 12; ++e) {
-            M64[o + e] = v[e];
-            M32[o + e] = (float)v[e];
+        for (int e = 0; e < 10; ++e) {
+            M64[(t * 10 + e) * nirr + q] = v[e];
+            M32[(t * 10 + e) * nirr + q] = (float)v[e];
         }
     }
 }
@@ -322,7 +322,8 @@ __device__ __forceinline__ double d0_tet(const double (&Lc)[8], int corner) {
 }
 
 __global__ void k_d0(int64_t nX, int n0, int n1, int n2, const int32_t *jlist, const int32_t *vmat,
-                     const double *irr_L64, double scale, double *d0, double *d0is64, float *d0is32) {
+                     const double *irr_L64, int64_t nirr, double scale, double *d0, double *d0is64,
+                     float *d0is32) {
     const int64_t jn = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (jn >= nX) return;
     const int64_t node = jlist[jn];
@@ -335,7 +336,7 @@ __global__ void k_d0(int64_t nX, int n0, int n1, int n2, const int32_t *jlist, c
         const int64_t q = -(int64_t)m - 1;
         double Lc[8];
 #pragma unroll
-        for (int cc = 0; cc < 8; ++cc) Lc[cc] = irr_L64[q * 8 + cc];
+        for (int cc = 0; cc < 8; ++cc) Lc[cc] = irr_L64[cc * nirr + q];
         acc += d0_tet<0>(Lc, c) + d0_tet<1>(Lc, c) + d0_tet<2>(Lc, c) + d0_tet<3>(Lc, c) + d0_tet<4>(Lc, c) +
                d0_tet<5>(Lc, c);
     }
@@ -485,8 +486,8 @@ int run_setup(xfft_problem *p, const double *L_dev_raw) {
             hipMalloc(&p->irr_lab, sizeof(int32_t) * 12 * nirr) != hipSuccess ||
             hipMalloc(&p->t64.irr_L, sizeof(double) * 8 * nirr) != hipSuccess ||
             hipMalloc(&p->t32.irr_L, sizeof(float) * 8 * nirr) != hipSuccess ||
-            hipMalloc(&p->t64.irr_M, sizeof(double) * 72 * nirr) != hipSuccess ||
-            hipMalloc(&p->t32.irr_M, sizeof(float) * 72 * nirr) != hipSuccess ||
+            hipMalloc(&p->t64.irr_M, sizeof(double) * 60 * nirr) != hipSuccess ||
+            hipMalloc(&p->t32.irr_M, sizeof(float) * 60 * nirr) != hipSuccess ||
             hipMalloc(&p->d0, sizeof(double) * nX) != hipSuccess ||
             hipMalloc(&p->t64.d0is, sizeof(double) * nX) != hipSuccess ||
             hipMalloc(&p->t32.d0is, sizeof(float) * nX) != hipSuccess ||
@@ -502,7 +503,7 @@ int run_setup(xfft_problem *p, const double *L_dev_raw) {
     }
     if (!rc && g.nX > 0) {
         k_d0<<<(unsigned)((g.nX + tb - 1) / tb), tb, 0, s>>>(g.nX, g.n0, g.n1, g.n2, p->jlist, p->vmat, p->t64.irr_L,
-                                                             p->d0_scale, p->d0, p->t64.d0is, p->t32.d0is);
+                                                             g.nirr, p->d0_scale, p->d0, p->t64.d0is, p->t32.d0is);
         k_enr_src<<<(unsigned)((g.nX + tb - 1) / tb), tb, 0, s>>>(g.nX, g.n0, g.n1, g.n2, p->jlist, p->vmat,
                                                                   p->enr_src);
     }
