@@ -371,6 +371,12 @@ bool is_unit_basis(int nload, const double *E) {
     return true;
 }
 
+// x[i] *= a (displacements from voxel units to units of len)
+__global__ void k_scale(double *x, int64_t n, double a) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) x[i] *= a;
+}
+
 int solve_impl(xfft_problem *p, int nload, const double *strain, double *disp, double *stress, double *avg_stress,
                double *c_eff, xfft_stats *stats, bool device_out) {
     if (!p || nload < 1 || !strain) return XFFT_EINVAL;
@@ -416,6 +422,8 @@ int solve_impl(xfft_problem *p, int nload, const double *strain, double *disp, d
             HIP_OK(hipStreamSynchronize(s));
             if (device_out) {
                 HIP_OK(hipMemcpyAsync(disp + (size_t)3 * N * l0, p->w64.u, sizeof(double) * 3 * N * nr, k_out, s));
+                const int64_t nd = 3 * N * nr;
+                k_scale<<<(unsigned)((nd + 255) / 256), 256, 0, s>>>(disp + (size_t)3 * N * l0, nd, p->h);
             } else {
                 HIP_OK(hipMemcpyAsync(disp + (size_t)3 * N * l0, p->w64.u, sizeof(double) * 3 * N * nr, k_out, s));
                 HIP_OK(hipStreamSynchronize(s));
@@ -442,11 +450,6 @@ int solve_impl(xfft_problem *p, int nload, const double *strain, double *disp, d
         }
     }
     if (stress && !device_out && vstress_dev) (void)hipFree(vstress_dev);
-    if (device_out && disp) {
-        // scale device displacements by h
-        // (small host round trip avoided: use a copy through the work buffer is unnecessary;
-        //  the caller receives voxel-unit values scaled below)
-    }
     if (unit) p->sol_unit_basis = true;
     if (avg_stress) {
         if (device_out) HIP_OK(hipMemcpy(avg_stress, avg.data(), sizeof(double) * 6 * nload, hipMemcpyHostToDevice));

@@ -77,6 +77,14 @@ def _lib():
         return _LIB
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2601_02172_amd.build`")
+    # PyTorch ships its own HIP runtime under the same soname.  Loading it first
+    # makes the library bind to that instance, so that one HIP runtime serves
+    # the process and torch device buffers and streams can be passed to the
+    # C ABI; loaded the other way round, two runtimes would compete for the GPU.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(LIB_PATH)
     P, D, I32, I64, V = (ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32),
                          ctypes.POINTER(ctypes.c_int64), ctypes.c_void_p)

@@ -222,6 +222,27 @@ def test_displacement_and_stress_outputs_consistent():
     assert np.abs(r["disp"].mean(axis=2)).max() < 1e-13
 
 
+def test_device_buffer_solve_matches_host_solve():
+    # xfft_solve_device (torch device buffers) returns what xfft_solve returns,
+    # displacements in units of len (h != 1 here)
+    import torch
+    from paper_2601_02172_amd import Problem
+    n, L, ph, lame = _case("two_spheres_36x24x18")
+    h = 0.5
+    E = np.eye(6)[[0, 3, 5]]
+    with Problem(n, [v * h for v in n], L * h, ph, lame, rtol=1e-11) as p:
+        r = p.solve(E, disp=True)
+        dev = torch.device("cuda:0")
+        strain = torch.tensor(E, dtype=torch.float64, device=dev).contiguous()
+        disp = torch.full((3, 3, p.N), float("nan"), dtype=torch.float64, device=dev)
+        avg = torch.full((3, 6), float("nan"), dtype=torch.float64, device=dev)
+        torch.cuda.synchronize()
+        p.solve_device(strain.data_ptr(), 3, disp.data_ptr(), avg.data_ptr())
+        d_dev, a_dev = disp.cpu().numpy(), avg.cpu().numpy()
+    np.testing.assert_allclose(a_dev, r["avg_stress"], rtol=0, atol=1e-13 * np.abs(r["avg_stress"]).max())
+    np.testing.assert_allclose(d_dev, r["disp"], rtol=0, atol=1e-13 * np.abs(r["disp"]).max())
+
+
 def _golden(case):
     path = os.path.join(GOLDEN, f"oracle_{case}.json")
     if not os.path.exists(path):
