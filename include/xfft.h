@@ -176,7 +176,11 @@ int xfft_get_layout(xfft_problem *p, int64_t *info, int64_t *jlist, double *d0);
  * Classes: 0 irregular-voxel operator, 1 regular-voxel operator, 2 enriched
  * gather, 3 FFT x forward (+ residual update), 4 FFT y forward, 5 FFT z +
  * Green multiply + inverse z, 6 FFT y inverse, 7 FFT x inverse (+ CG update),
- * 8 enriched residual, 9 enriched CG update, 10 scalar recurrences.
+ * 8 enriched residual, 9 enriched CG update, 10 scalar recurrences.  Work
+ * that runs inside another class's launch is timed there and its own class
+ * counts no launches: the enriched gather always (class 1), the enriched
+ * residual with the compile-time z pass (class 5), the enriched CG update with
+ * the xy-plane kernels (class 7).
  * precision: XFFT_FP64 or XFFT_FP32.  Overwrites the problem's work fields. */
 int xfft_profile(xfft_problem *p, int32_t precision, int32_t nrhs, int32_t nrep, double *ms_out,
                  int32_t *count_out);
