@@ -505,14 +505,11 @@ __global__ __launch_bounds__(256) void k_fft_y_t(FftArgs A, const cpx<T> *tw, cp
 }
 
 // ---------------------------------------------------------------- xy plane kernels (n0 == n1 == N)
-// A workgroup transforms whole (component, z plane, load) planes held in LDS:
+// A workgroup transforms one (component, z plane, load) plane held in LDS:
 // the x transform runs on row pairs packed as complex lines, the y transform on
-// the kx columns.  Spectrum layout [c][ky][kz][kx] (kx fastest).  The grid is
-// persistent (PIPE: about two workgroups per CU, each taking every gridDim-th
-// plane): the global loads of the next plane are issued into registers before
-// the current plane is transformed, so HBM traffic overlaps the LDS and ALU
-// work of the transform.  Without PIPE there is one workgroup per plane.
-// LDS uses the interleaved layout of fft_lines.h (line l at l * (N | 1), no
+// the kx columns.  Spectrum layout [c][ky][kz][kx] (kx fastest).  In FP32 the
+// kernels need at most 64 registers, so two 1024-thread workgroups share a CU
+// and one's loads and stores overlap the other's transform.  LDS uses the interleaved layout of fft_lines.h (line l at l * (N | 1), no
 // padding), so the transposes between the x and y transforms, which address
 // 32 consecutive lines at one offset or one line at 32 consecutive offsets,
 // are conflict free as well.
@@ -536,12 +533,6 @@ template <int N> struct PlaneCfg {
     static constexpr int SW = FP ? N / RS : 1;     // spectrum sweeps per plane
     static constexpr int XW = FP ? NP / RS : 1;    // split sweeps per plane
 };
-
-// next plane index >= q (stride gridDim.x) of an active right-hand side
-__device__ __forceinline__ int next_plane(const FftArgs &A, int q, int per_r, int total) {
-    while (q < total && !active_rhs(A, q / per_r)) q += gridDim.x;
-    return q;
-}
 
 // LDS holds the packed row pairs of a plane: x transform, split into the two
 // real rows' spectra, transpose to kx-major lines, y transform, store.
@@ -621,72 +612,43 @@ __device__ __forceinline__ void plane_forward_core(cpx<T> *sh, const cpx<T> *tw,
     }
 }
 
-template <typename T, int N, bool PIPE>
+template <typename T, int N>
 __global__ __launch_bounds__(1024) void k_fft_plane_fwd(FftArgs A, const cpx<T> *tw, T *f, const T *z,
                                                          cpx<T> *spec, int nrhs) {
     using C = PlaneCfg<N>;
     extern __shared__ unsigned char smem_raw[];
     cpx<T> *sh = reinterpret_cast<cpx<T> *>(smem_raw);
-    const int per_r = 3 * A.n2, total = per_r * nrhs;
+    const int per_r = 3 * A.n2;
+    const int q = (int)xcd_remap(blockIdx.x, gridDim.x);
+    const int r = q / per_r, plane = q - r * per_r;
+    if (!active_rhs(A, r)) return;
+    const int c = plane / A.n2, kz = plane - c * A.n2;
     int tid = threadIdx.x;
-    T va[C::PE], vb[C::PE], wa[C::PE], wb[C::PE];
-    auto fetch = [&](int q) {
-        const int r = q / per_r, plane = q - r * per_r;
-        const T *fr = f + (int64_t)r * 3 * A.N + (int64_t)plane * N * N;
-        const T *zr = z ? z + (int64_t)r * 3 * A.N + (int64_t)plane * N * N : nullptr;
+    // opaque to the optimiser: the index arithmetic of each phase is recomputed
+    // from tid instead of being kept live across the transform (fewer registers)
+    asm volatile("" : "+v"(tid));
+    T *fr = f + (int64_t)r * 3 * A.N + (int64_t)plane * N * N;
+    const T *zr = z ? z + (int64_t)r * 3 * A.N + (int64_t)plane * N * N : nullptr;
+    const T alpha = z ? (T)A.scal[r].alpha : (T)0;
+    // fused residual update f -= alpha z; pack row pairs
 #pragma unroll
-        for (int i = 0; i < C::PE; ++i) {
-            const int idx = tid + i * C::NT;
-            if (C::NIN % C::NT == 0 || idx < C::NIN) {
-                const int pp = idx / N, x = idx - pp * N;
-                const int o0 = (2 * pp) * N + x;
-                va[i] = fr[o0];
-                vb[i] = fr[o0 + N];
-                if (zr) { wa[i] = zr[o0]; wb[i] = zr[o0 + N]; }
+    for (int i = 0; i < C::PE; ++i) {
+        const int idx = tid + i * C::NT;
+        if (C::NIN % C::NT == 0 || idx < C::NIN) {
+            const int pp = idx / N, x = idx - pp * N;
+            const int o0 = (2 * pp) * N + x;
+            T a = fr[o0], b = fr[o0 + N];
+            if (zr) {
+                a -= alpha * zr[o0];
+                b -= alpha * zr[o0 + N];
+                fr[o0] = a;
+                fr[o0 + N] = b;
             }
-        }
-    };
-    int q = PIPE ? next_plane(A, blockIdx.x, per_r, total) : (int)blockIdx.x;
-    if (!PIPE && !active_rhs(A, q / per_r)) return;
-    if (q < total) fetch(q);      // a persistent workgroup may have no active plane at all
-    while (q < total) {
-        // index arithmetic is recomputed per plane instead of being kept live
-        // in registers across the whole loop
-        asm volatile("" : "+v"(tid));
-        const int r = q / per_r, plane = q - r * per_r;
-        const int c = plane / A.n2, kz = plane - c * A.n2;
-        T *fr = f + (int64_t)r * 3 * A.N + (int64_t)plane * N * N;
-        const T alpha = z ? (T)A.scal[r].alpha : (T)0;
-        // fused residual update f -= alpha z; pack row pairs
-#pragma unroll
-        for (int i = 0; i < C::PE; ++i) {
-            const int idx = tid + i * C::NT;
-            if (C::NIN % C::NT == 0 || idx < C::NIN) {
-                const int pp = idx / N, x = idx - pp * N;
-                const int o0 = (2 * pp) * N + x;
-                T a = va[i], b = vb[i];
-                if (z) {
-                    a -= alpha * wa[i];
-                    b -= alpha * wb[i];
-                    fr[o0] = a;
-                    fr[o0 + N] = b;
-                }
-                sh[pp * C::LS + x] = {a, b};
-            }
-        }
-        if constexpr (!PIPE) {
-            __syncthreads();
-            plane_forward_core<T, N>(sh, tw, A, spec + (int64_t)r * 3 * A.specN + (int64_t)c * A.specN, kz, tid);
-            return;
-        } else {
-            const int qn = next_plane(A, q + gridDim.x, per_r, total);
-            if (qn < total) fetch(qn);
-            __syncthreads();
-            plane_forward_core<T, N>(sh, tw, A, spec + (int64_t)r * 3 * A.specN + (int64_t)c * A.specN, kz, tid);
-            __syncthreads();
-            q = qn;
+            sh[pp * C::LS + x] = {a, b};
         }
     }
+    __syncthreads();
+    plane_forward_core<T, N>(sh, tw, A, spec + (int64_t)r * 3 * A.specN + (int64_t)c * A.specN, kz, tid);
 }
 
 // LDS holds the kx-major half spectrum of a plane: y inverse transform,
@@ -747,13 +709,12 @@ __device__ __forceinline__ void plane_inverse_core(cpx<T> *sh, const cpx<T> *tw,
 }
 
 // mode 0: out = G f; mode 1: u += alpha d, d = G f + beta d; mode 2: d = G f
-template <typename T, int N, bool PIPE>
+template <typename T, int N>
 __global__ __launch_bounds__(1024) void k_fft_plane_inv(FftArgs A, const cpx<T> *tw, const cpx<T> *spec, int mode,
                                                          T *out, T *u, T *d, int nrhs, EnrFin<T> E) {
     using C = PlaneCfg<N>;
     extern __shared__ unsigned char smem_raw[];
     cpx<T> *sh = reinterpret_cast<cpx<T> *>(smem_raw);
-    const int per_r = 3 * A.n2, total = per_r * nrhs;
     int tid = threadIdx.x;
     if (E.mode) {
         // enriched direction update, spread over the whole grid
@@ -761,108 +722,58 @@ __global__ __launch_bounds__(1024) void k_fft_plane_inv(FftArgs A, const cpx<T> 
             if (active_rhs(A, r))
                 enr_final_rows<T>(E, A.scal, r, (int64_t)blockIdx.x * C::NT + tid, (int64_t)gridDim.x * C::NT);
     }
-    cpx<T> sp[C::PS];
-    auto fetch = [&](int q) {
-        const int r = q / per_r, plane = q - r * per_r;
-        const int c = plane / A.n2, kz = plane - c * A.n2;
-        const cpx<T> *sr = spec + (int64_t)r * 3 * A.specN + (int64_t)c * A.specN;
-        if constexpr (C::FP) {
-            const int kxl = tid % C::KW, kyl = tid / C::KW;
-            const cpx<T> *si = sr + ((int64_t)kyl * A.n2 + kz) * C::NH + kxl;
-            const int64_t sstep = (int64_t)C::RS * A.n2 * C::NH;
+    const int per_r = 3 * A.n2;
+    const int q = (int)xcd_remap(blockIdx.x, gridDim.x);
+    const int r = q / per_r, plane = q - r * per_r;
+    if (!active_rhs(A, r)) return;
+    const int c = plane / A.n2, kz = plane - c * A.n2;
+    // opaque to the optimiser: index arithmetic is recomputed per phase (fewer registers)
+    asm volatile("" : "+v"(tid));
+    const cpx<T> *sr = spec + (int64_t)r * 3 * A.specN + (int64_t)c * A.specN;
+    if constexpr (C::FP) {
+        const int kxl = tid % C::KW, kyl = tid / C::KW;
+        const cpx<T> *si = sr + ((int64_t)kyl * A.n2 + kz) * C::NH + kxl;
+        const int64_t sstep = (int64_t)C::RS * A.n2 * C::NH;
+        const int st = kxl * C::LS + kyl;
 #pragma unroll
-            for (int m = 0; m < C::SW; ++m) sp[m] = si[m * sstep];
-            if (tid < N) sp[C::SW] = sr[((int64_t)tid * A.n2 + kz) * C::NH + C::KW];
-            return;
-        }
+        for (int m = 0; m < C::SW; ++m) sh[st + m * C::RS] = si[m * sstep];
+        if (tid < N) sh[C::KW * C::LS + tid] = sr[((int64_t)tid * A.n2 + kz) * C::NH + C::KW];
+    } else {
 #pragma unroll
         for (int i = 0; i < C::PS; ++i) {
             const int idx = tid + i * C::NT;
             if (C::NSP % C::NT == 0 || idx < C::NSP) {
                 const int ky = idx / C::NH, kx = idx - ky * C::NH;
-                sp[i] = sr[((int64_t)ky * A.n2 + kz) * C::NH + kx];
+                sh[kx * C::LS + ky] = sr[((int64_t)ky * A.n2 + kz) * C::NH + kx];
             }
         }
-    };
-    int q = PIPE ? next_plane(A, blockIdx.x, per_r, total) : (int)blockIdx.x;
-    if (!PIPE && !active_rhs(A, q / per_r)) return;
-    if (q < total) fetch(q);      // a persistent workgroup may have no active plane at all
-    while (q < total) {
-        // index arithmetic is recomputed per plane instead of being kept live
-        // in registers across the whole loop
-        asm volatile("" : "+v"(tid));
-        const int r = q / per_r, plane = q - r * per_r;
-        if constexpr (C::FP) {
-            const int kxl = tid % C::KW, kyl = tid / C::KW;
-            const int st = kxl * C::LS + kyl;
+    }
+    __syncthreads();
+    plane_inverse_core<T, N>(sh, tw, tid);
+    const int64_t base = (int64_t)r * 3 * A.N + (int64_t)plane * N * N;
+    T alpha = 0, beta = 0;
+    if (mode == 1) { alpha = (T)A.scal[r].alpha; beta = (T)A.scal[r].beta; }
 #pragma unroll
-            for (int m = 0; m < C::SW; ++m) sh[st + m * C::RS] = sp[m];
-            if (tid < N) sh[C::KW * C::LS + tid] = sp[C::SW];
-        } else {
-#pragma unroll
-            for (int i = 0; i < C::PS; ++i) {
-                const int idx = tid + i * C::NT;
-                if (C::NSP % C::NT == 0 || idx < C::NSP) {
-                    const int ky = idx / C::NH, kx = idx - ky * C::NH;
-                    sh[kx * C::LS + ky] = sp[i];
-                }
+    for (int i = 0; i < C::PE; ++i) {
+        const int idx = tid + i * C::NT;
+        if (C::NIN % C::NT == 0 || idx < C::NIN) {
+            const int pp = idx / N, x = idx - pp * N;
+            const cpx<T> yv = sh[pp * C::LS + x];
+            const int64_t o0 = base + (unsigned)((2 * pp) * N + x), o1 = o0 + N;
+            if (mode == 0) {
+                out[o0] = yv.x;
+                out[o1] = yv.y;
+            } else if (mode == 1) {
+                const T d0 = d[o0], d1 = d[o1];
+                u[o0] += alpha * d0;
+                u[o1] += alpha * d1;
+                d[o0] = yv.x + beta * d0;
+                d[o1] = yv.y + beta * d1;
+            } else {
+                d[o0] = yv.x;
+                d[o1] = yv.y;
             }
         }
-        const int64_t base = (int64_t)r * 3 * A.N + (int64_t)plane * N * N;
-        // PIPE: the CG update's loads of d and u of this plane are issued now,
-        // with those of the next plane's spectrum, ahead of the transform
-        T da[C::PE], db[C::PE], ua[C::PE], ub[C::PE];
-        int qn = total;
-        if constexpr (PIPE) {
-            if (mode == 1) {
-#pragma unroll
-                for (int i = 0; i < C::PE; ++i) {
-                    const int idx = tid + i * C::NT;
-                    if (C::NIN % C::NT == 0 || idx < C::NIN) {
-                        const int pp = idx / N, x = idx - pp * N;
-                        const int64_t o0 = base + (unsigned)((2 * pp) * N + x);
-                        da[i] = d[o0]; db[i] = d[o0 + N];
-                        ua[i] = u[o0]; ub[i] = u[o0 + N];
-                    }
-                }
-            }
-            qn = next_plane(A, q + gridDim.x, per_r, total);
-            if (qn < total) fetch(qn);
-        }
-        __syncthreads();
-        plane_inverse_core<T, N>(sh, tw, tid);
-        T alpha = 0, beta = 0;
-        if (mode == 1) { alpha = (T)A.scal[r].alpha; beta = (T)A.scal[r].beta; }
-#pragma unroll
-        for (int i = 0; i < C::PE; ++i) {
-            const int idx = tid + i * C::NT;
-            if (C::NIN % C::NT == 0 || idx < C::NIN) {
-                const int pp = idx / N, x = idx - pp * N;
-                const cpx<T> yv = sh[pp * C::LS + x];
-                const int64_t o0 = base + (unsigned)((2 * pp) * N + x), o1 = o0 + N;
-                if (mode == 0) {
-                    out[o0] = yv.x;
-                    out[o1] = yv.y;
-                } else if (mode == 1) {
-                    T d0, d1, u0, u1;
-                    if constexpr (PIPE) {
-                        d0 = da[i]; d1 = db[i]; u0 = ua[i]; u1 = ub[i];
-                    } else {
-                        d0 = d[o0]; d1 = d[o1]; u0 = u[o0]; u1 = u[o1];
-                    }
-                    u[o0] = u0 + alpha * d0;
-                    u[o1] = u1 + alpha * d1;
-                    d[o0] = yv.x + beta * d0;
-                    d[o1] = yv.y + beta * d1;
-                } else {
-                    d[o0] = yv.x;
-                    d[o1] = yv.y;
-                }
-            }
-        }
-        if constexpr (!PIPE) return;
-        __syncthreads();
-        q = qn;
     }
 }
 
@@ -1077,34 +988,24 @@ template <typename K> static void allow_lds(K kernel, size_t bytes) {
     if (bytes > 65536) (void)hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
-// pipelined persistent grid for FP32 (the FP64 variant would need more
-// registers than 1024-thread workgroups allow)
-template <typename T> static constexpr bool plane_pipe() { return sizeof(T) == 4; }
-template <typename T> static unsigned plane_grid(const xfft_problem *p, int nrhs) {
-    const int total = 3 * p->g.n2 * nrhs;
-    if (!plane_pipe<T>()) return (unsigned)total;
-    const int g = 2 * p->num_cu;
-    return (unsigned)(total < g ? total : g);
-}
+// one workgroup per (load, component, z plane); two are resident per CU
+static unsigned plane_grid(const xfft_problem *p, int nrhs) { return (unsigned)(3 * p->g.n2 * nrhs); }
 
 template <typename T, int N>
 static void plane_fwd(const xfft_problem *p, FftArgs A, int nrhs, hipStream_t s, const cpx<T> *tw, T *f,
                       const T *z, cpx<T> *spec) {
-    constexpr bool PIPE = plane_pipe<T>();
     const size_t lds = (size_t)PlaneCfg<N>::ELEMS * sizeof(cpx<T>);
     static bool init = false;
-    if (!init) { allow_lds(k_fft_plane_fwd<T, N, PIPE>, lds); init = true; }
-    k_fft_plane_fwd<T, N, PIPE><<<plane_grid<T>(p, nrhs), PlaneCfg<N>::NT, lds, s>>>(A, tw, f, z, spec, nrhs);
+    if (!init) { allow_lds(k_fft_plane_fwd<T, N>, lds); init = true; }
+    k_fft_plane_fwd<T, N><<<plane_grid(p, nrhs), PlaneCfg<N>::NT, lds, s>>>(A, tw, f, z, spec, nrhs);
 }
 template <typename T, int N>
 static void plane_inv(const xfft_problem *p, FftArgs A, int nrhs, hipStream_t s, const cpx<T> *tw,
                       const cpx<T> *spec, int mode, T *out, T *u, T *d, const EnrFin<T> &E) {
-    constexpr bool PIPE = plane_pipe<T>();
     const size_t lds = (size_t)PlaneCfg<N>::ELEMS * sizeof(cpx<T>);
     static bool init = false;
-    if (!init) { allow_lds(k_fft_plane_inv<T, N, PIPE>, lds); init = true; }
-    k_fft_plane_inv<T, N, PIPE><<<plane_grid<T>(p, nrhs), PlaneCfg<N>::NT, lds, s>>>(A, tw, spec, mode, out, u, d,
-                                                                                     nrhs, E);
+    if (!init) { allow_lds(k_fft_plane_inv<T, N>, lds); init = true; }
+    k_fft_plane_inv<T, N><<<plane_grid(p, nrhs), PlaneCfg<N>::NT, lds, s>>>(A, tw, spec, mode, out, u, d, nrhs, E);
 }
 template <typename T, int N2>
 static void zpass(const xfft_problem *p, FftArgs A, int nrhs, hipStream_t s, const Tables<T> &tb, cpx<T> *spec,
