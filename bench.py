@@ -270,8 +270,8 @@ def main():
         print(json.dumps(pmc_summary(*args.pmc_summary), indent=1))
         return
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              "(load cases and RVEs would be sharded across GPUs, see DESIGN.md)", file=sys.stderr)
+        print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported "
+              "(load cases and RVEs would be sharded across GPUs)", file=sys.stderr)
         sys.exit(2)
 
     import torch

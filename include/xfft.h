@@ -62,7 +62,8 @@ typedef struct {
                            iterative refinement); default XFFT_FP64 */
     double snap_eps;    /* |L|/h below this is set to 0 (Sec. 3 reads 1e-6; default 1e-6) */
     double d0_scale;    /* multiplies every D0_jj; the converged result is independent (default 1) */
-    double inner_rtol;  /* mixed: residual reduction of each inner FP32 solve (default 1e-6: two outer steps reach 1e-10) */
+    double inner_rtol;  /* mixed: residual reduction of each inner FP32 solve (default 1e-6); an inner solve also
+                           ends once its residual meets half the outer tolerance rtol */
     int32_t batch;      /* 1: all loads of a call iterate together; 0: one load at a time (default 1) */
     int32_t device;     /* HIP device ordinal (default 0) */
     int32_t check_every;/* host polls convergence every this many iterations (default 8; rounded up to even) */

@@ -1,7 +1,7 @@
 """Full-size checks on the benchmark workloads (128^3 spheres, 256^3 ellipsoids),
 in the launch configuration bench.py times.  The oracle cannot run at these
 sizes, so the checks are properties that hold at any size: the mixed-precision
-C_eff against the FP64 path (spec tolerance 1e-8 relative), symmetry and
+C_eff against the FP64 path (mixed-precision tolerance 1e-8 relative), symmetry and
 positive definiteness of C_eff, the Voigt and Reuss bounds of a conforming
 Galerkin method (Appendix A), symmetry of the operator and of the
 preconditioner, and the gradient of the two precisions against each other.
