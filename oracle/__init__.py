@@ -25,8 +25,10 @@ What it computes (voxel units, h = 1; Sec. 2 and Sec. 3 of the paper):
                      assembled stencil (eqs. constantCoefficientPreconditioner,
                      GreenHermitian).
 * ``solver``      -- the displacement-based linear CG of Algorithm 1 with the
-                     stopping criterion of eq. stoppingCriterion, and a dense
-                     least-squares solve for tiny grids.
+                     stopping criterion of eq. stoppingCriterion, the basic,
+                     Barzilai-Borwein and nonlinear CG schemes with the step
+                     size of eq. stepsize, and a dense least-squares solve for
+                     tiny grids.
 * ``homogenize``  -- effective stiffness from the average stress, the energy
                      form and its closed-form derivative with respect to the
                      per-phase Lame parameters.

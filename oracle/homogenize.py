@@ -17,11 +17,16 @@ import numpy as np
 
 from .system import System
 from .green import GreenOperator
-from .solver import pcg, dense_solve
+from .solver import pcg, dense_solve, fft_scheme, step_size, SCHEMES
 
 
 def solve_loads(disc, loads, tol=1e-12, maxit=5000, method="pcg"):
-    """Solve the scaled system for every macro strain; returns (U, infos)."""
+    """Solve the scaled system for every macro strain; returns (U, infos).
+
+    method: "pcg" (Algorithm 1), "dense", or one of the schemes of
+    solver.fft_scheme ("lcg", "nlcg", "bb", "basic") with the step size of
+    eq. stepsize.
+    """
     sysm = System(disc)
     loads = np.atleast_2d(np.asarray(loads, dtype=np.float64))
     U, infos = [], []
@@ -33,6 +38,14 @@ def solve_loads(disc, loads, tol=1e-12, maxit=5000, method="pcg"):
             infos.append(dict(iters=0, sigma=sysm.average_stress(u, eb)))
         return np.array(U), infos
     green = GreenOperator(disc.n)
+    if method in SCHEMES:
+        s0 = step_size(disc.lame)
+        for eb in loads:
+            u, info = fft_scheme(sysm.apply, sysm.rhs(eb), lambda f: green.apply(f, disc.nX),
+                                 lambda x: sysm.average_stress(x, eb), disc.volume, tol, maxit, method, s0)
+            U.append(u)
+            infos.append(info)
+        return np.array(U), infos
     for eb in loads:
         u, info = pcg(sysm.apply, sysm.rhs(eb), lambda f: green.apply(f, disc.nX),
                       lambda x: sysm.average_stress(x, eb), disc.volume, tol, maxit)
