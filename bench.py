@@ -262,6 +262,9 @@ def main():
     ap.add_argument("--inner-rtol", type=float, default=1e-6)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--schemes", action="store_true",
+                    help="also time the FP64 solution schemes (linear CG, nonlinear CG, Barzilai-Borwein, basic), "
+                         "6 loads batched, one step each")
     ap.add_argument("--workload", default="spheres128", choices=["spheres128", "ellipsoids256", "uneven16"])
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="summarise two rocprofv3 --pmc runs of this script (FETCH_SIZE, WRITE_SIZE) as JSON")
@@ -342,6 +345,24 @@ def main():
                     iters=[int(v) for v in r64["iters"]])
         log(f"fp64 plain: {fp64['ms_per_step']:.1f} ms/step, iters {fp64['iters']}")
 
+    schemes = None
+    if args.schemes:
+        schemes = {}
+        for name in ("lcg", "nlcg", "bb", "basic"):
+            ps = Problem(cfg["n"], cfg["length"], cfg["L"], cfg["phase"], cfg["lame"], rtol=args.rtol,
+                         precision="fp64", scheme=name, maxit=20000)
+            ps.solve(E[:1])
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rs = ps.solve(E, c_eff=True)
+            torch.cuda.synchronize()
+            ts = time.perf_counter() - t0
+            ps.close()
+            schemes[name] = dict(ms_per_step=round(1000.0 * ts, 3), solves_per_s=round(6.0 / ts, 4),
+                                 iters=[int(v) for v in rs["iters"]], converged=bool(rs["converged"]),
+                                 c_eff=rs["c_eff"])
+            log(f"scheme {name} (fp64, 6 loads batched): {1000.0 * ts:.1f} ms, iters {schemes[name]['iters']}")
+
     # accuracy of both paths against a reference C_eff
     golden = os.path.join(ROOT, "tests", "golden", f"oracle_{args.workload}.json")
     if os.path.exists(golden):
@@ -357,6 +378,9 @@ def main():
     err_fp64 = float(np.linalg.norm(r64["c_eff"] - C_ref) / nrm) if fp64 else None
 
     log(f"C_eff rel error vs {ref_kind}: mixed {err_mixed:.2e}, fp64 {err_fp64}")
+    if schemes:
+        for v in schemes.values():
+            v["c_eff_rel_error"] = float(np.linalg.norm(v.pop("c_eff") - C_ref) / nrm)
     # dominant kernel of the timed region: largest total time among all launches
     byts = {"fp32": algorithmic_bytes(lay, 4, 6), "fp64": algorithmic_bytes(lay, 8, 6)}
     totals = {k: m * c for k, (m, c) in region.items()}
@@ -450,6 +474,7 @@ def main():
         "kernels": kernels,
         "timed_region_kernels": region_summary,
         "loss_gradient": grad_info,
+        "schemes": schemes,
     }
     print(json.dumps(out))
 

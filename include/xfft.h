@@ -53,6 +53,18 @@ enum {
 
 enum { XFFT_FP64 = 0, XFFT_MIXED = 1, XFFT_FP32 = 2 /* step-level entry points only */ };
 
+/* Solution schemes (Sec. 3, solvers).  All share the operator, the
+ * preconditioner and the stopping criterion of Algorithm 1 and differ in the
+ * step alpha and the direction weight beta of an iteration; s0 is the step
+ * size of eq. stepsize, 2 / (C_- + C_+) over the stiffness eigenvalues
+ * (3 lambda + 2 mu and 2 mu) of all phases.
+ *   XFFT_LCG    linear CG (Algorithm 1): alpha = res^2 / <A d, d>, beta = res_new^2 / res^2
+ *   XFFT_NLCG   nonlinear CG: fixed step alpha = s0, Fletcher-Reeves beta = res_new^2 / res^2
+ *   XFFT_BB     Barzilai-Borwein: beta = 0, alpha = <s, P s> / <s, A s> of the previous update s
+ *               (the previous iteration's res^2 / <A d, d>); the first step is s0
+ *   XFFT_BASIC  basic scheme: beta = 0, alpha = s0 (Richardson iteration u += s0 P^-1 f) */
+enum { XFFT_LCG = 0, XFFT_NLCG = 1, XFFT_BB = 2, XFFT_BASIC = 3 };
+
 typedef struct xfft_problem xfft_problem;
 
 typedef struct {
@@ -71,6 +83,8 @@ typedef struct {
                            replayed (default 1); 0: launched one by one */
     int32_t autotune;   /* 1: at the first solve, time the operator's tile depths and keep the fastest (default 1) */
     void *stream;       /* hipStream_t to run on, or NULL for a library-owned stream */
+    int32_t scheme;     /* XFFT_LCG (default), XFFT_NLCG, XFFT_BB or XFFT_BASIC; schemes other than
+                           XFFT_LCG need precision XFFT_FP64 */
 } xfft_options;
 
 typedef struct {

@@ -90,13 +90,27 @@ int ensure_state(xfft_problem *p, int cap) {
     return XFFT_OK;
 }
 
+// Step size of eq. stepsize: 2 / (C_- + C_+), C_-/C_+ the smallest/largest
+// eigenvalue of the phase stiffnesses (3 lambda + 2 mu once, 2 mu five times).
+double step_size(const std::vector<double> &lame) {
+    double cmin = INFINITY, cmax = -INFINITY;
+    for (size_t q = 0; q + 1 < lame.size(); q += 2) {
+        const double a = 3.0 * lame[q] + 2.0 * lame[q + 1], b = 2.0 * lame[q + 1];
+        cmin = std::fmin(cmin, std::fmin(a, b));
+        cmax = std::fmax(cmax, std::fmax(a, b));
+    }
+    return 2.0 / (cmin + cmax);
+}
+
 // Upload per-rhs macro strains and reset scalars / flags.
 int reset_state(xfft_problem *p, int nrhs, const double *ebar_host) {
     std::vector<Scalars> sc(nrhs);
+    const double s0 = step_size(p->lame_host);
     for (int r = 0; r < nrhs; ++r) {
         std::memset(&sc[r], 0, sizeof(Scalars));
         sc[r].tol = p->rtol;
         sc[r].tol_inner = p->inner_rtol;
+        sc[r].s0 = s0;
     }
     HIP_OK(hipMemcpyAsync(p->scal, sc.data(), sizeof(Scalars) * nrhs, hipMemcpyHostToDevice, p->stream));
     HIP_OK(hipMemsetAsync(p->flags, 0, sizeof(Flags) * nrhs, p->stream));
@@ -596,6 +610,7 @@ void xfft_default_options(xfft_options *opt) {
     opt->use_graph = 1;
     opt->autotune = 1;
     opt->stream = nullptr;
+    opt->scheme = XFFT_LCG;
 }
 
 const char *xfft_strerror(int code) {
@@ -660,7 +675,8 @@ int xfft_setup(const int32_t n[3], const double len[3], const double *levelset, 
     if (opt_in) opt = *opt_in;
     if (!(opt.rtol > 0.0) || opt.maxit < 1 || !(opt.snap_eps >= 0.0) || !(opt.d0_scale > 0.0) ||
         !(opt.inner_rtol > 0.0 && opt.inner_rtol < 1.0) ||
-        (opt.precision != XFFT_FP64 && opt.precision != XFFT_MIXED))
+        (opt.precision != XFFT_FP64 && opt.precision != XFFT_MIXED) || opt.scheme < XFFT_LCG ||
+        opt.scheme > XFFT_BASIC || (opt.scheme != XFFT_LCG && opt.precision != XFFT_FP64))
         return XFFT_EINVAL;
     const double t0 = now_s();
     int ndev = 0;
@@ -681,6 +697,7 @@ int xfft_setup(const int32_t n[3], const double len[3], const double *levelset, 
     p->maxit = opt.maxit; p->precision = opt.precision; p->batch = opt.batch; p->check_every = opt.check_every;
     p->use_graph = opt.use_graph != 0;
     p->autotune = opt.autotune != 0;
+    p->scheme = opt.scheme;
     if (opt.stream) {
         p->stream = (hipStream_t)opt.stream;
     } else {

@@ -11,6 +11,7 @@
 // tracked), so the second test ends the last inner solve as soon as its
 // recursive residual meets the outer tolerance, instead of after a full
 // tol_inner reduction.
+#include "xfft.h"
 #include "kernels.h"
 #include "enriched.h"
 
@@ -32,6 +33,7 @@ struct ScArgs {
     Flags *flags;
     double volume;
     int op, crit, parity, maxit;
+    int scheme;           // XFFT_LCG, XFFT_NLCG, XFFT_BB or XFFT_BASIC
     double *sum_out;      // [rhs][7] or null
 };
 
@@ -89,7 +91,16 @@ __global__ __launch_bounds__(256) void k_scalars(ScArgs A) {
             S.alpha = 0.0;
             return;
         }
-        const double alpha = S.res2 / zd;
+        // step of the scheme (Sec. 3, solvers): linear CG takes the exact line
+        // search, the basic scheme and nonlinear CG the fixed step s0, and
+        // Barzilai-Borwein the line-search step of the previous iteration
+        double alpha = S.res2 / zd;
+        if (A.scheme == XFFT_NLCG || A.scheme == XFFT_BASIC) {
+            alpha = S.s0;
+        } else if (A.scheme == XFFT_BB) {
+            alpha = S.alpha_lag > 0.0 ? S.alpha_lag : S.s0;
+            S.alpha_lag = S.res2 / zd;
+        }
         S.alpha = alpha;
         S.sigma[0] += alpha * v[1] / A.volume; S.sigma[1] += alpha * v[2] / A.volume;
         S.sigma[2] += alpha * v[3] / A.volume;
@@ -97,7 +108,9 @@ __global__ __launch_bounds__(256) void k_scalars(ScArgs A) {
         S.sigma[5] += alpha * r2 * v[6] / A.volume;
     } else if (A.op == SC_BETA) {
         const double rn = v[0];
-        S.beta = (S.res2 > 0.0) ? rn / S.res2 : 0.0;
+        // the basic and Barzilai-Borwein schemes step along y = P^-1 f
+        const bool cg = A.scheme == XFFT_LCG || A.scheme == XFFT_NLCG;
+        S.beta = (cg && S.res2 > 0.0) ? rn / S.res2 : 0.0;
         S.res2 = rn;
         F.iters += 1;
         double sn = 0.0;
@@ -173,6 +186,7 @@ void launch_scalars(xfft_problem *p, int op, int crit, int nrhs, int parity, dou
     A.crit = crit;
     A.parity = parity;
     A.maxit = p->maxit;
+    A.scheme = p->scheme;
     A.sum_out = sum_out;
     xfft_prof_mark(p, -1, s);
     k_scalars<<<nrhs, 256, 0, s>>>(A);

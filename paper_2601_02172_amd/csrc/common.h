@@ -154,6 +154,8 @@ struct Scalars {           // per right-hand side, device resident
     double sigma[6];
     double tol;            // tolerance of eq. stoppingCriterion (criterion 0)
     double tol_inner;      // residual reduction of an inner refinement solve (criterion 1)
+    double s0;             // step size of eq. stepsize (schemes other than linear CG)
+    double alpha_lag;      // Barzilai-Borwein: step of the next iteration (0: none yet)
 };
 
 struct Flags {
@@ -188,6 +190,7 @@ struct xfft_problem {
     // options
     double rtol, snap_eps, d0_scale, inner_rtol;
     int maxit, precision, batch, check_every;
+    int scheme = 0;        // XFFT_LCG, XFFT_NLCG, XFFT_BB or XFFT_BASIC
     // geometry (device)
     double *Ls = nullptr;          // snapped level set, voxel units [N]
     int32_t *phase = nullptr;      // [N]

@@ -18,6 +18,7 @@ XFFT_EINVAL, XFFT_ENOMEM, XFFT_EDEVICE, XFFT_EBREAKDOWN = -1, -2, -3, -4
 XFFT_FP64, XFFT_MIXED, XFFT_FP32 = 0, 1, 2
 
 _PREC = {"fp64": XFFT_FP64, "mixed": XFFT_MIXED, "fp32": XFFT_FP32}
+_SCHEME = {"lcg": 0, "nlcg": 1, "bb": 2, "basic": 3}
 
 
 class XfftError(RuntimeError):
@@ -40,6 +41,7 @@ class Options(ctypes.Structure):
         ("use_graph", ctypes.c_int32),
         ("autotune", ctypes.c_int32),
         ("stream", ctypes.c_void_p),
+        ("scheme", ctypes.c_int32),
     ]
 
 
@@ -147,7 +149,7 @@ class Problem:
 
     def __init__(self, n, length, levelset, phase, lame, *, rtol=1e-10, maxit=20000, precision="fp64",
                  snap_eps=1e-6, d0_scale=1.0, inner_rtol=1e-6, batch=True, device=0, check_every=8,
-                 use_graph=True, autotune=True, stream=None):
+                 use_graph=True, autotune=True, stream=None, scheme="lcg"):
         lib = _lib()
         self._h = None
         n = np.ascontiguousarray(n, dtype=np.int32)
@@ -166,6 +168,7 @@ class Problem:
         o.batch, o.device, o.check_every = int(bool(batch)), device, check_every
         o.use_graph, o.autotune = int(bool(use_graph)), int(bool(autotune))
         o.stream = stream
+        o.scheme = _SCHEME[scheme]
         h = ctypes.c_void_p()
         _check(lib.xfft_setup(_ip(n), _dp(length), _dp(L), _ip(ph), self.nphase, _dp(lame), ctypes.byref(o),
                               ctypes.byref(h)), "xfft_setup")

@@ -37,7 +37,7 @@ def test_default_options_and_strerror():
         assert len(lib.xfft_strerror(code)) > 0
 
 
-def _setup_rc(n, length, L, ph, lame):
+def _setup_rc(n, length, L, ph, lame, opt=None):
     lib = X._lib()
     n = np.ascontiguousarray(n, dtype=np.int32)
     length = np.ascontiguousarray(length, dtype=np.float64)
@@ -45,8 +45,8 @@ def _setup_rc(n, length, L, ph, lame):
     ph = np.ascontiguousarray(ph, dtype=np.int32)
     lame = np.ascontiguousarray(lame, dtype=np.float64)
     h = ctypes.c_void_p()
-    rc = lib.xfft_setup(X._ip(n), X._dp(length), X._dp(L), X._ip(ph), lame.shape[0], X._dp(lame), None,
-                        ctypes.byref(h))
+    rc = lib.xfft_setup(X._ip(n), X._dp(length), X._dp(L), X._ip(ph), lame.shape[0], X._dp(lame),
+                        None if opt is None else ctypes.byref(opt), ctypes.byref(h))
     if rc == 0:
         lib.xfft_destroy(h)
     return rc
@@ -84,6 +84,17 @@ def test_setup_rejects_invalid_input(case):
         n = [1024, 1024, 1024]
         length = [1024.0] * 3
     assert _setup_rc(n, length, L, ph, lame) == X.XFFT_EINVAL
+
+
+@pytest.mark.parametrize("scheme,precision", [(4, X.XFFT_FP64), (-1, X.XFFT_FP64), (1, X.XFFT_MIXED),
+                                              (2, X.XFFT_MIXED), (3, X.XFFT_MIXED)])
+def test_setup_rejects_invalid_scheme(scheme, precision):
+    # options are checked before any device call; only linear CG runs inside the mixed refinement
+    o = pkg.default_options()
+    assert o.scheme == 0
+    o.scheme, o.precision = scheme, precision
+    assert _setup_rc([8, 8, 8], [8.0] * 3, np.ones(512), np.zeros(512, dtype=np.int32), np.array([[1.0, 0.5]]),
+                     o) == X.XFFT_EINVAL
 
 
 def test_setup_without_device_reports_device_error():
