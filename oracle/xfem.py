@@ -14,9 +14,13 @@ Steps, in the paper's order:
    abs enrichment); enriched shape functions N_X^j = N^j rho (eq. enrichedN).
 4. Cut elements are split along the plane L_h = 0 into subtetrahedra, each
    integrated by the degree-2 four-point rule (Sec. 3, subdivision).
-5. Scaling factors D0_jj = int ||grad^s N_X^j||^2 (eq. scaling factors), read
-   literally as the squared Frobenius norm of the Voigt-Mandel matrix
-   M (grad N_X^j (x) I_3), summed over the quadrature points.
+5. Scaling factors D0_jj = int ||grad^s N_X^j||^2 (eq. scaling factors).  N_X^j
+   is a scalar function, and the norm is read as that of its gradient,
+   D0_jj = int |grad N_X^j|^2, summed over the quadrature points.  With this
+   reading linear CG needs the 46-50 iterations the paper reports for the
+   Hashin inclusion (Sec. 4.1, iteration count); the Frobenius norm of the
+   Voigt-Mandel matrix M (grad N_X^j (x) I_3), twice as large, needs 53-66.
+   The converged solution does not depend on D0.
 6. Element matrices A_e = sum_q w B^T C B, S_e = sum_q w C B (eqs. Kapp_q,
    Sapp_q) with B = M (grad N (x) I_3) (eq. shapeFunctionGradient).
 
@@ -155,11 +159,10 @@ def cut_element_qps(X, Lv, pts, wts):
 
 
 def d0_contributions(qps):
-    """Per-vertex contribution of one element to D0_jj = int ||M (grad N_X^j (x) I3)||_F^2."""
+    """Per-vertex contribution of one element to D0_jj = int |grad N_X^j|^2."""
     D = np.zeros(4)
     for (w, gX, _) in qps:
-        Ba = mandel_B(gX)                                # (4, 6, 3)
-        D += w * np.sum(Ba * Ba, axis=(1, 2))
+        D += w * np.sum(gX * gX, axis=1)                 # gX: (4, 3)
     return D
 
 

@@ -340,7 +340,10 @@ __global__ void k_d0(int64_t nX, int n0, int n1, int n2, const int32_t *jlist, c
         acc += d0_tet<0>(Lc, c) + d0_tet<1>(Lc, c) + d0_tet<2>(Lc, c) + d0_tet<3>(Lc, c) + d0_tet<4>(Lc, c) +
                d0_tet<5>(Lc, c);
     }
-    const double D = 2.0 * acc * scale;
+    // eq. scaling factors with the norm of the scalar function's gradient:
+    // D0_jj = int |grad N_X^j|^2 (the reading that gives the paper's iteration
+    // counts for the Hashin inclusion, Sec. 4.1)
+    const double D = acc * scale;
     d0[jn] = D;
     d0is64[jn] = 1.0 / sqrt(D);
     d0is32[jn] = (float)(1.0 / sqrt(D));

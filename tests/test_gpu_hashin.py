@@ -1,0 +1,72 @@
+"""Hashin's neutral inclusion on the GPU (Sec. 4.1): the paper's own test case.
+
+A coated sphere (core radius 6/5 e, coating radius 2 pi, cell edge 16, bulk
+moduli 1 / 0.808024 / 8.080240 from the composite-sphere formula, Poisson's
+ratio 0.25) under the macro strain I has the exact effective bulk modulus 1.
+
+* Accuracy: the error of K_eff stays below an O(h^2) envelope fitted at N = 16
+  (the paper observes O(h^2)), for N = 16 ... 256.
+* Iterations: linear CG to tol 1e-7 needs 46-50 iterations in the paper, stable
+  in N; the GPU path stays within 44-55 for every N (soft pin of the preconditioner
+  and of the D0 reading).
+* Schemes at N = 128, tol 1e-7 (the paper's solver study): every scheme reaches
+  the tolerance, the basic scheme needs the most iterations and linear CG the
+  fewest.
+"""
+
+import numpy as np
+import pytest
+
+from microstructure.shapes import coated_sphere_levelset
+
+pytestmark = pytest.mark.gpu
+
+EB = np.array([1.0, 1.0, 1.0, 0.0, 0.0, 0.0])
+
+
+def _hashin(N):
+    n = (N, N, N)
+    h = 16.0 / N
+    c = np.array([8.0, 8.0, 8.0]) / h
+    L, ph = coated_sphere_levelset(n, c, 6.0 / 5.0 * np.e / h, 2.0 * np.pi / h)
+    f = (6.0 / 5.0 * np.e / (2.0 * np.pi)) ** 3
+    Kc = (6.0 - 5.0 * f) / (6.0 + 4.0 * f)
+    K = np.array([1.0, Kc, 10.0 * Kc])
+    lame = np.stack([0.6 * K, 0.6 * K], axis=1)          # nu = 0.25: lambda = mu = 0.6 K
+    return n, L * h, ph, lame
+
+
+def _solve(N, **kw):
+    from paper_2601_02172_amd import Problem
+    n, L, ph, lame = _hashin(N)
+    with Problem(n, [16.0] * 3, L, ph, lame, **kw) as p:
+        r = p.solve(EB)
+    assert r["converged"]
+    return r["avg_stress"][0][:3].sum() / 9.0, int(r["iters"][0])
+
+
+def test_hashin_bulk_modulus_error_within_h2_envelope():
+    errs = {}
+    for N in (16, 32, 64, 128, 256):
+        K, _ = _solve(N, rtol=1e-10)
+        errs[N] = abs(K - 1.0)
+        print(f"N {N}: |K_eff - 1| = {errs[N]:.3e}", flush=True)
+    for N in (32, 64, 128, 256):
+        assert errs[N] <= 2.0 * errs[16] * (16.0 / N) ** 2
+
+
+def test_hashin_linear_cg_iterations_match_paper():
+    for N in (16, 32, 64, 128, 256):
+        _, it = _solve(N, rtol=1e-7)
+        print(f"N {N}: {it} iterations", flush=True)
+        assert 44 <= it <= 55
+
+
+def test_hashin_schemes_reach_tolerance_in_paper_order():
+    its = {}
+    for scheme in ("lcg", "nlcg", "bb", "basic"):
+        K, its[scheme] = _solve(128, rtol=1e-7, scheme=scheme, maxit=5000)
+        assert abs(K - 1.0) < 1e-5
+    print(its, flush=True)
+    assert its["basic"] == max(its.values())
+    assert its["lcg"] == min(its.values())
