@@ -235,3 +235,33 @@ def rsa_ellipsoids(n, count, axes, gap, rng, max_tries=20000):
         centers.append(c)
         rots.append(R)
     return np.array(centers), np.array(rots)
+
+
+def rotation_xyz(deg):
+    """Rotation by ``deg`` degrees about x, then about y, then about z (R = Rz Ry Rx)."""
+    a = np.deg2rad(deg)
+    c, s = np.cos(a), np.sin(a)
+    Rx = np.array([[1, 0, 0], [0, c, -s], [0, s, c]])
+    Ry = np.array([[c, 0, s], [0, 1, 0], [-s, 0, c]])
+    Rz = np.array([[c, -s, 0], [s, c, 0], [0, 0, 1]])
+    return Rz @ Ry @ Rx
+
+
+def cube_levelset(n, center, edge, R=None):
+    """Signed distance to one cube (edge length ``edge``, voxel units) centred at
+    ``center``, its axes rotated by R (columns: the cube's axes in the cell frame).
+
+    Exact Euclidean distance to the box outside, minus the distance to the
+    nearest face inside; periodic images are taken by the nearest-image offset,
+    which is exact while the cube and its distance band fit in the cell.
+    """
+    x, y, z = node_coords(n)
+    off = np.stack([periodic_delta(x, center[0], n[0]), periodic_delta(y, center[1], n[1]),
+                    periodic_delta(z, center[2], n[2])], axis=-1)
+    p = off if R is None else off @ np.asarray(R, dtype=np.float64)      # coordinates in the cube frame
+    q = np.abs(p) - 0.5 * edge
+    outside = np.sqrt(np.sum(np.maximum(q, 0.0) ** 2, axis=-1))
+    inside = np.minimum(np.max(q, axis=-1), 0.0)
+    L = (outside + inside).reshape(-1)
+    phase = np.where(L < 0.0, 1, 0).astype(np.int32)
+    return L.astype(np.float64), phase

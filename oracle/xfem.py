@@ -18,7 +18,7 @@ Steps, in the paper's order:
    is a scalar function, and the norm is read as that of its gradient,
    D0_jj = int |grad N_X^j|^2, summed over the quadrature points.  With this
    reading linear CG needs the 46-50 iterations the paper reports for the
-   Hashin inclusion (Sec. 4.1, iteration count); the Frobenius norm of the
+   Hashin inclusion (Sec. 4.2, iteration count); the Frobenius norm of the
    Voigt-Mandel matrix M (grad N_X^j (x) I_3), twice as large, needs 53-66.
    The converged solution does not depend on D0.
 6. Element matrices A_e = sum_q w B^T C B, S_e = sum_q w C B (eqs. Kapp_q,

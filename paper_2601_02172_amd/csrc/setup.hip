@@ -342,7 +342,7 @@ __global__ void k_d0(int64_t nX, int n0, int n1, int n2, const int32_t *jlist, c
     }
     // eq. scaling factors with the norm of the scalar function's gradient:
     // D0_jj = int |grad N_X^j|^2 (the reading that gives the paper's iteration
-    // counts for the Hashin inclusion, Sec. 4.1)
+    // counts for the Hashin inclusion, Sec. 4.2)
     const double D = acc * scale;
     d0[jn] = D;
     d0is64[jn] = 1.0 / sqrt(D);

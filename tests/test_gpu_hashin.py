@@ -1,4 +1,4 @@
-"""Hashin's neutral inclusion on the GPU (Sec. 4.1): the paper's own test case.
+"""Hashin's neutral inclusion on the GPU (Sec. 4.2): the paper's own test case.
 
 A coated sphere (core radius 6/5 e, coating radius 2 pi, cell edge 16, bulk
 moduli 1 / 0.808024 / 8.080240 from the composite-sphere formula, Poisson's
