@@ -34,11 +34,12 @@ HBM_PEAK_GBS = 8000.0
 # one add, multiply or fused multiply-add per lane and cycle (FP32 and FP64 alike)
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # arithmetic operations per voxel of the regular-voxel operator (six Kuhn tets by
-# their 12 shared edges): 36 edge differences, 6 x 18 per tet (3 shear sums,
-# trace, 3 normal and 3 shear stresses, 6 edge-force accumulations), 48 for the
-# corner forces from the edge forces, 24 for the node sums and the sign, 3 for
-# lambda V, mu V and 2 mu V
-REGULAR_OPS_PER_VOXEL = 36 + 6 * 18 + 48 + 24 + 3
+# their 12 shared edges): 36 edge differences, 6 x 12 per tet (3 shear sums,
+# trace, 3 normal and 3 shear stresses), 18 edge-force accumulations (the 9
+# first-edge and 9 last-edge values each collect two tets; the middle edges one),
+# 48 for the corner forces from the edge forces, 24 for the node sums and the
+# sign, 3 for lambda V, mu V and 2 mu V
+REGULAR_OPS_PER_VOXEL = 36 + 6 * 12 + 18 + 48 + 24 + 3
 # copy-like calibration kernel for the HBM byte counters: elementwise negation of
 # a float32 buffer reads and writes exactly COPY_BYTES each
 COPY_BYTES = 256 << 20

@@ -35,6 +35,14 @@ template <typename T> struct Sym {
 
 template <typename T> __device__ __forceinline__ Sym<T> sym_zero() { return {0, 0, 0, 0, 0, 0}; }
 
+// Start value of a sum: -0 is the exact additive identity (x + (-0) == x for
+// every x, -0 included; +0 is not, since -0 + +0 = +0), so the compiler drops
+// the first addition into an accumulator that starts from it.
+template <typename T> __device__ __forceinline__ constexpr T acc_zero() { return -(T)0; }
+template <typename T> __device__ __forceinline__ Sym<T> sym_acc_zero() {
+    return {acc_zero<T>(), acc_zero<T>(), acc_zero<T>(), acc_zero<T>(), acc_zero<T>(), acc_zero<T>()};
+}
+
 // Mandel 6-vector (11,22,33,sqrt2 23,sqrt2 13,sqrt2 12) -> tensor components
 template <typename T> __device__ __forceinline__ Sym<T> from_mandel(const T *m) {
     const T r = (T)0.70710678118654752440;

@@ -142,8 +142,8 @@ __device__ __forceinline__ void regular_voxel(const T (&U)[8][3], const T (&eb)[
         for (int a = 0; a < 3; ++a) {
             E.first[a][i] = U[1 << a][i] - U[0][i];
             E.last[a][i] = U[7][i] - U[7 ^ (1 << a)][i];
-            G.first[a][i] = (T)0;
-            G.last[a][i] = (T)0;
+            G.first[a][i] = acc_zero<T>();
+            G.last[a][i] = acc_zero<T>();
 #pragma unroll
             for (int b = 0; b < 3; ++b)
                 if (a != b) E.mid[a][b][i] = U[(1 << a) | (1 << b)][i] - U[1 << a][i];
@@ -346,7 +346,7 @@ __global__ __launch_bounds__(256) void k_regular(OpArgs<T> A) {
             }
             const T V = (T)(1.0 / 6.0);
             const T lamV = V * A.lame[2 * m], muV = V * A.lame[2 * m + 1];
-            Sym<T> S = sym_zero<T>();
+            Sym<T> S = sym_acc_zero<T>();
             regular_voxel<T, EB, ST>(U, eb, lamV, muV, F, S);
             if (ST && owner && kl >= k0) {
                 add_sym(acc7, S);
@@ -473,7 +473,7 @@ __device__ __forceinline__ void irregular_tet(const T (&Lc)[8], const T *__restr
         G[p2] = w[3] - w[2];
         Sym<T> Sh[4];
 #pragma unroll
-        for (int d = 0; d < 4; ++d) Sh[d] = sym_zero<T>();
+        for (int d = 0; d < 4; ++d) Sh[d] = sym_acc_zero<T>();
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
             Grad<T> K;
@@ -490,7 +490,7 @@ __device__ __forceinline__ void irregular_tet(const T (&Lc)[8], const T *__restr
 #pragma unroll
             for (int d = 0; d < 4; ++d) sym_axpy(Sh[d], Mrow[d], sc);
         }
-        Sym<T> St = sym_zero<T>(), Sw = sym_zero<T>();
+        Sym<T> St = sym_acc_zero<T>(), Sw = sym_acc_zero<T>();
 #pragma unroll
         for (int d = 0; d < 4; ++d) {
             sym_axpy(St, (T)1, Sh[d]);
@@ -547,8 +547,8 @@ __global__ __launch_bounds__(128) void k_irregular(OpArgs<T> A) {
 #pragma unroll
         for (int c = 0; c < 8; ++c)
 #pragma unroll
-            for (int d = 0; d < 3; ++d) F[c][d] = Fe[c][d] = (T)0;
-        Sym<T> S = sym_zero<T>();
+            for (int d = 0; d < 3; ++d) F[c][d] = Fe[c][d] = acc_zero<T>();
+        Sym<T> S = sym_acc_zero<T>();
         irregular_tet<0, T, EB>(Lc, A.irr_M, A.nirr, q32, U, Q, lab, A.lame, eb, F, Fe, S);
         irregular_tet<1, T, EB>(Lc, A.irr_M, A.nirr, q32, U, Q, lab, A.lame, eb, F, Fe, S);
         irregular_tet<2, T, EB>(Lc, A.irr_M, A.nirr, q32, U, Q, lab, A.lame, eb, F, Fe, S);
