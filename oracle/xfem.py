@@ -183,10 +183,18 @@ class Discretization:
     sample_cut : timing only -- build just the first ``sample_cut`` cut elements
         (the rest get zero element matrices) and record the time per element in
         ``timing``; the resulting system is NOT the discretisation.
+    discretization : "xfem" (the method) or "p1", the voxel-segmented P1
+        Galerkin FEM of the paper's comparison table (Sec. 4.1): no enrichment,
+        each voxel one material.  The paper does not state how a voxel gets its
+        material; here the level set at the voxel centre (the mean of its eight
+        corner values, the trilinear interpolant there) picks the side, and the
+        voxel takes the label of its corner with the largest |L| on that side
+        (L >= 0 for a centre value >= 0, else L < 0), ties to the corner with the
+        smallest x + 2 y + 4 z offset.
     """
 
     def __init__(self, n, length, L, phase, lame, snap_eps=1e-6, d0_scale=1.0, rule="degree2",
-                 keep_qp=True, sample_cut=None):
+                 keep_qp=True, sample_cut=None, discretization="xfem"):
         import time
         t_start = time.perf_counter()
         self.n = tuple(int(v) for v in n)
@@ -222,12 +230,19 @@ class Discretization:
                 vn[:, t, a] = ((i + off[0]) % n0) + n0 * (((j + off[1]) % n1) + n1 * ((k + off[2]) % n2))
         self.vert_nodes = vn
 
+        if discretization not in ("xfem", "p1"):
+            raise ValueError(f"unknown discretization {discretization!r}")
+        self.discretization = discretization
         Lv = Ls[vn]
-        self.cut = np.any(Lv > 0, axis=2) & np.any(Lv < 0, axis=2)
-        # uncut material: vertex with the largest |L|, first along the path on ties
-        amax = np.argmax(np.abs(Lv), axis=2)
-        lab_nodes = self.phase[vn]
-        self.tet_label = np.take_along_axis(lab_nodes, amax[..., None], axis=2)[..., 0]
+        if discretization == "p1":
+            self.cut = np.zeros((self.N, 6), dtype=bool)
+            self.tet_label = np.repeat(self._voxel_labels(i, j, k)[:, None], 6, axis=1)
+        else:
+            self.cut = np.any(Lv > 0, axis=2) & np.any(Lv < 0, axis=2)
+            # uncut material: vertex with the largest |L|, first along the path on ties
+            amax = np.argmax(np.abs(Lv), axis=2)
+            lab_nodes = self.phase[vn]
+            self.tet_label = np.take_along_axis(lab_nodes, amax[..., None], axis=2)[..., 0]
         if np.any(self.tet_label < 0) or np.any(self.tet_label >= len(self.lame)):
             raise ValueError("phase label out of range")
 
@@ -250,6 +265,24 @@ class Discretization:
         t_end = time.perf_counter()
         self.timing = dict(uncut=t_mid - t_start, cut=t_end - t_mid,
                            cut_built=len(self.cut_voxel) if sample_cut is None else min(sample_cut, len(self.cut_voxel)))
+
+    def _voxel_labels(self, i, j, k):
+        """Voxel materials of the P1 voxel-segmented discretisation (see the class doc)."""
+        n0, n1, n2 = self.n
+        Lc, pc = [], []
+        for c in range(8):                      # corner offsets (c & 1, (c >> 1) & 1, c >> 2)
+            node = ((i + (c & 1)) % n0) + n0 * (((j + ((c >> 1) & 1)) % n1) + n1 * ((k + (c >> 2)) % n2))
+            Lc.append(self.Ls[node])
+            pc.append(self.phase[node])
+        centre = np.mean(Lc, axis=0)
+        best = np.full(self.N, -1.0)
+        lab = pc[0].copy()
+        for c in range(8):
+            on_side = np.where(centre >= 0.0, Lc[c] >= 0.0, Lc[c] < 0.0)
+            better = on_side & (np.abs(Lc[c]) > best)
+            best = np.where(better, np.abs(Lc[c]), best)
+            lab = np.where(better, pc[c], lab)
+        return lab
 
     # ------------------------------------------------------------------ cut elements
     def _build_cut_elements(self, d0_scale):
