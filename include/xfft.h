@@ -65,6 +65,15 @@ enum { XFFT_FP64 = 0, XFFT_MIXED = 1, XFFT_FP32 = 2 /* step-level entry points o
  *   XFFT_BASIC  basic scheme: beta = 0, alpha = s0 (Richardson iteration u += s0 P^-1 f) */
 enum { XFFT_LCG = 0, XFFT_NLCG = 1, XFFT_BB = 2, XFFT_BASIC = 3 };
 
+/* Discretisations (Sec. 4.1, Tab. discretizations).
+ *   XFFT_XFEM  the X-FEM discretisation of the method (default)
+ *   XFFT_P1    voxel-segmented P1 Galerkin FEM on the same six elements per voxel: no enrichment, one
+ *              material per voxel.  The voxel's side is the sign of the level set at its centre (the
+ *              mean of its eight corner values); it takes the label of its corner with the largest |L|
+ *              on that side (L >= 0 for a centre value >= 0, else L < 0), ties to the corner with the
+ *              smallest x + 2y + 4z offset. */
+enum { XFFT_XFEM = 0, XFFT_P1 = 1 };
+
 typedef struct xfft_problem xfft_problem;
 
 typedef struct {
@@ -85,6 +94,7 @@ typedef struct {
     void *stream;       /* hipStream_t to run on, or NULL for a library-owned stream */
     int32_t scheme;     /* XFFT_LCG (default), XFFT_NLCG, XFFT_BB or XFFT_BASIC; schemes other than
                            XFFT_LCG need precision XFFT_FP64 */
+    int32_t discretization; /* XFFT_XFEM (default) or XFFT_P1 */
 } xfft_options;
 
 typedef struct {

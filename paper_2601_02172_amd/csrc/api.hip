@@ -611,6 +611,7 @@ void xfft_default_options(xfft_options *opt) {
     opt->autotune = 1;
     opt->stream = nullptr;
     opt->scheme = XFFT_LCG;
+    opt->discretization = XFFT_XFEM;
 }
 
 const char *xfft_strerror(int code) {
@@ -676,7 +677,8 @@ int xfft_setup(const int32_t n[3], const double len[3], const double *levelset, 
     if (!(opt.rtol > 0.0) || opt.maxit < 1 || !(opt.snap_eps >= 0.0) || !(opt.d0_scale > 0.0) ||
         !(opt.inner_rtol > 0.0 && opt.inner_rtol < 1.0) ||
         (opt.precision != XFFT_FP64 && opt.precision != XFFT_MIXED) || opt.scheme < XFFT_LCG ||
-        opt.scheme > XFFT_BASIC || (opt.scheme != XFFT_LCG && opt.precision != XFFT_FP64))
+        opt.scheme > XFFT_BASIC || (opt.scheme != XFFT_LCG && opt.precision != XFFT_FP64) ||
+        (opt.discretization != XFFT_XFEM && opt.discretization != XFFT_P1))
         return XFFT_EINVAL;
     const double t0 = now_s();
     int ndev = 0;
@@ -698,6 +700,7 @@ int xfft_setup(const int32_t n[3], const double len[3], const double *levelset, 
     p->use_graph = opt.use_graph != 0;
     p->autotune = opt.autotune != 0;
     p->scheme = opt.scheme;
+    p->p1 = opt.discretization == XFFT_P1 ? 1 : 0;
     if (opt.stream) {
         p->stream = (hipStream_t)opt.stream;
     } else {

@@ -191,6 +191,7 @@ struct xfft_problem {
     double rtol, snap_eps, d0_scale, inner_rtol;
     int maxit, precision, batch, check_every;
     int scheme = 0;        // XFFT_LCG, XFFT_NLCG, XFFT_BB or XFFT_BASIC
+    int p1 = 0;            // 1: voxel-segmented P1 discretisation (no enrichment)
     // geometry (device)
     double *Ls = nullptr;          // snapped level set, voxel units [N]
     int32_t *phase = nullptr;      // [N]

@@ -55,7 +55,7 @@ __device__ __forceinline__ void classify_tet(const double (&Lc)[8], const int (&
     element_labels<double>(L, lab, lab_uncut, lp, ln, ml);
 }
 
-__global__ void k_classify(int n0, int n1, int n2, const double *Ls, const int32_t *phase, uint8_t *vflag,
+__global__ void k_classify(int n0, int n1, int n2, const double *Ls, const int32_t *phase, int p1, uint8_t *vflag,
                            int32_t *vlab, uint8_t *jflag, unsigned long long *counts) {
     const int64_t N = (int64_t)n0 * n1 * n2;
     const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -69,6 +69,25 @@ __global__ void k_classify(int n0, int n1, int n2, const double *Ls, const int32
         nodes[c] = corner_node(i, j, k, c, n0, n1, n2);
         Lc[c] = Ls[nodes[c]];
         pc[c] = phase[nodes[c]];
+    }
+    if (p1) {
+        // voxel-segmented P1: the level set at the voxel centre (mean of the
+        // corners) picks the side; the corner with the largest |L| on that side
+        // gives the material (first in corner order on ties)
+        double sum = 0.0;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) sum += Lc[c];
+        const bool pos = sum >= 0.0;
+        double best = -1.0;
+        int lab = pc[0];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            const bool on = pos ? Lc[c] >= 0.0 : Lc[c] < 0.0;
+            if (on && fabs(Lc[c]) > best) { best = fabs(Lc[c]); lab = pc[c]; }
+        }
+        vflag[v] = 0;
+        vlab[v] = lab;
+        return;
     }
     bool cut[6], ml[6];
     int lu[6], lp[6], ln[6];
@@ -474,7 +493,7 @@ int run_setup(xfft_problem *p, const double *L_dev_raw) {
         cleanup();
         return XFFT_EINVAL_INTERNAL;
     }
-    k_classify<<<nbN, tb, 0, s>>>(g.n0, g.n1, g.n2, p->Ls, p->phase, vflag, vlab, jflag, counts);
+    k_classify<<<nbN, tb, 0, s>>>(g.n0, g.n1, g.n2, p->Ls, p->phase, p->p1, vflag, vlab, jflag, counts);
     rc = compact(s, N, vflag, p->vmat, vlab, &p->irr, &g.nirr);
     if (!rc) rc = compact(s, N, jflag, jmap, nullptr, &p->jlist, &g.nX);
     unsigned long long hc[2] = {0, 0};

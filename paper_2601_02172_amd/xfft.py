@@ -42,6 +42,7 @@ class Options(ctypes.Structure):
         ("autotune", ctypes.c_int32),
         ("stream", ctypes.c_void_p),
         ("scheme", ctypes.c_int32),
+        ("discretization", ctypes.c_int32),
     ]
 
 
@@ -149,7 +150,7 @@ class Problem:
 
     def __init__(self, n, length, levelset, phase, lame, *, rtol=1e-10, maxit=20000, precision="fp64",
                  snap_eps=1e-6, d0_scale=1.0, inner_rtol=1e-6, batch=True, device=0, check_every=8,
-                 use_graph=True, autotune=True, stream=None, scheme="lcg"):
+                 use_graph=True, autotune=True, stream=None, scheme="lcg", discretization="xfem"):
         lib = _lib()
         self._h = None
         n = np.ascontiguousarray(n, dtype=np.int32)
@@ -169,6 +170,7 @@ class Problem:
         o.use_graph, o.autotune = int(bool(use_graph)), int(bool(autotune))
         o.stream = stream
         o.scheme = _SCHEME[scheme]
+        o.discretization = {"xfem": 0, "p1": 1}[discretization]
         h = ctypes.c_void_p()
         _check(lib.xfft_setup(_ip(n), _dp(length), _dp(L), _ip(ph), self.nphase, _dp(lame), ctypes.byref(o),
                               ctypes.byref(h)), "xfft_setup")
