@@ -79,8 +79,11 @@ int ensure_state(xfft_problem *p, int cap) {
     if (p->flags) (void)hipFree(p->flags);
     if (p->ebar) (void)hipFree(p->ebar);
     if (p->host_flags) (void)hipHostFree(p->host_flags);
+    if (p->sum7) (void)hipFree(p->sum7);
     p->partial = nullptr; p->scal = nullptr; p->flags = nullptr; p->ebar = nullptr; p->host_flags = nullptr;
+    p->sum7 = nullptr;
     if (hipMalloc(&p->partial, sizeof(double) * NPART * (size_t)p->nslots * cap) != hipSuccess ||
+        hipMalloc(&p->sum7, sizeof(double) * 7 * cap) != hipSuccess ||
         hipMalloc(&p->scal, sizeof(Scalars) * cap) != hipSuccess ||
         hipMalloc(&p->flags, sizeof(Flags) * cap) != hipSuccess ||
         hipMalloc(&p->ebar, sizeof(double) * 6 * cap) != hipSuccess ||
@@ -261,18 +264,26 @@ int autotune_depth(xfft_problem *p, Work<T> &w, const Tables<T> &tb, int nrhs) {
 }
 
 // Average stress (Mandel) of the FP64 iterate in w64.u for every rhs; optional voxel stress.
-int final_outputs(xfft_problem *p, int nrhs, double *avg_host, double *vstress_dev) {
+// <sigma> (and voxel stresses when vstress_dev is set) of the FP64 iterate.
+// sigma_ready: the scalars already hold the exact <sigma> of that iterate (the
+// last FP64 residual pass of the refinement loop computed it and the iterate
+// has not changed since), so without voxel stresses no further pass is needed.
+int final_outputs(xfft_problem *p, int nrhs, double *avg_host, double *vstress_dev, bool sigma_ready) {
     hipStream_t s = p->stream;
+    if (sigma_ready && !vstress_dev) {
+        std::vector<Scalars> sc(nrhs);
+        HIP_OK(hipMemcpyAsync(sc.data(), p->scal, sizeof(Scalars) * nrhs, hipMemcpyDeviceToHost, s));
+        HIP_OK(hipStreamSynchronize(s));
+        for (int r = 0; r < nrhs; ++r)
+            for (int q = 0; q < 6; ++q) avg_host[6 * r + q] = sc[r].sigma[q];
+        return XFFT_OK;
+    }
     Work<double> &w = p->w64;
     launch_operator<double>(p, w, p->t64, w.u, w.ue, w.z, w.ze, true, 1.0, nrhs, nullptr, 0, vstress_dev, s);
-    double *sum_dev = nullptr;
-    HIP_OK(hipMalloc(&sum_dev, sizeof(double) * 7 * nrhs));
-    launch_scalars(p, SC_SUM_ONLY, 0, nrhs, 0, sum_dev, s, true);
+    launch_scalars(p, SC_SUM_ONLY, 0, nrhs, 0, p->sum7, s, true);
     std::vector<double> sum(7 * nrhs);
-    hipError_t e1 = hipMemcpyAsync(sum.data(), sum_dev, sizeof(double) * 7 * nrhs, hipMemcpyDeviceToHost, s);
-    hipError_t e2 = hipStreamSynchronize(s);
-    (void)hipFree(sum_dev);
-    if (e1 != hipSuccess || e2 != hipSuccess) return XFFT_EDEVICE;
+    HIP_OK(hipMemcpyAsync(sum.data(), p->sum7, sizeof(double) * 7 * nrhs, hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
     const double V = (double)p->g.N, r2 = std::sqrt(2.0);
     for (int r = 0; r < nrhs; ++r) {
         const double *v = &sum[7 * r];
@@ -308,6 +319,7 @@ int solve_block(xfft_problem *p, int nrhs, const double *ebar_host, std::vector<
     const size_t nf = sizeof(double) * 3 * p->g.N * nrhs, ne = sizeof(double) * 3 * p->g.nX * nrhs;
     HIP_OK(hipMemsetAsync(w.u, 0, nf, s));
     if (ne) HIP_OK(hipMemsetAsync(w.ue, 0, ne, s));
+    p->sigma_ready = false;
     iters.assign(nrhs, 0);
     outer.assign(nrhs, 0);
     res_rel.assign(nrhs, 0.0);
@@ -344,7 +356,7 @@ int solve_block(xfft_problem *p, int nrhs, const double *ebar_host, std::vector<
             for (int r = 0; r < nrhs; ++r) {
                 if (!fl[r].pad[0]) { all_done = false; outer[r] = o + 1; }
             }
-            if (all_done) break;
+            if (all_done) { p->sigma_ready = true; break; }
             cg_loop<float>(p, w32, p->t32, nrhs, 1, &rc);
             if (rc) return rc;
             launch_accumulate_correction(p, nrhs, s);
@@ -426,7 +438,7 @@ int solve_impl(xfft_problem *p, int nload, const double *strain, double *disp, d
             else if (!vstress_dev && hipMalloc(&vstress_dev, sizeof(double) * 6 * N * blk) != hipSuccess)
                 return XFFT_ENOMEM;
         }
-        rc = final_outputs(p, nr, avg.data() + 6 * l0, stress ? vstress_dev : nullptr);
+        rc = final_outputs(p, nr, avg.data() + 6 * l0, stress ? vstress_dev : nullptr, p->sigma_ready);
         if (rc) return rc;
         hipStream_t s = p->stream;
         const hipMemcpyKind k_out = device_out ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
@@ -631,7 +643,7 @@ void xfft_destroy(xfft_problem *p) {
     (void)hipSetDevice(p->device);
     if (p->stream) (void)hipStreamSynchronize(p->stream);
     void *ptrs[] = {p->Ls, p->phase, p->vmat, p->irr, p->irr_j, p->irr_lab, p->jlist, p->enr_src, p->d0, p->partial,
-                    p->scal, p->flags, p->ebar, p->sol_u, p->sol_ue, p->t64.lame, p->t64.d0is, p->t64.irr_L,
+                    p->scal, p->flags, p->ebar, p->sum7, p->sol_u, p->sol_ue, p->t64.lame, p->t64.d0is, p->t64.irr_L,
                     p->t32.lame, p->t32.d0is, p->t32.irr_L, p->t64.irr_M, p->t32.irr_M};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
@@ -1063,7 +1075,7 @@ int xfft_batch_solve(xfft_problem *const *ps, int32_t nprob, double *c_eff, xfft
         rc = read_flags(p, nl, f);
         if (rc) break;
         std::vector<double> avg(6 * nl);
-        rc = final_outputs(p, nl, avg.data(), nullptr);
+        rc = final_outputs(p, nl, avg.data(), nullptr, false);
         if (rc) break;
         for (int k = 0; k < 6; ++k)
             for (int q = 0; q < 6; ++q) c_eff[36 * i + 6 * q + k] = avg[6 * k + q];

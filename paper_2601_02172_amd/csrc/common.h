@@ -212,6 +212,8 @@ struct xfft_problem {
     xfft::Work<double> w64;
     xfft::Work<float> w32;
     double *partial = nullptr;     // [cap][nslots][NPART]
+    double *sum7 = nullptr;        // [cap][7] sums of the output pass
+    bool sigma_ready = false;      // last solve_block left the exact <sigma> of its iterate in scal
     int part_cap = 0, nslots = 0;
     xfft::Scalars *scal = nullptr; // [cap]
     xfft::Flags *flags = nullptr;  // [cap]
