@@ -196,7 +196,7 @@ __device__ __forceinline__ double dpp_row_shr1(double v) {
 // voxels (a - dx, b - dy): corners 0/4 from its own voxel, 1/5 from the thread
 // at tx - 1, 2/6 from ty - 1 and 3/7 from (tx - 1, ty - 1).
 template <typename T, bool HX, bool EB, bool ST>
-__global__ __launch_bounds__(256) void k_regular(OpArgs<T> A) {
+__global__ __launch_bounds__(256, (sizeof(T) == 4 && !ST) ? 5 : 1) void k_regular(OpArgs<T> A) {
     __shared__ T Dp[3][TC * TC][3];
     __shared__ T FB[3][6][TE * TE];    // row sums for the node above, one buffer per layer of the unrolled march
     __shared__ double red[4 * 7];
@@ -293,10 +293,11 @@ __global__ __launch_bounds__(256) void k_regular(OpArgs<T> A) {
     mv[0] = elem(A.vmat, colv + plane_off(k0 - 1));
     mv[1] = (k0 < k1) ? elem(A.vmat, colv + plane_off(k0)) : 0;
     mv[2] = 0;
-    // buffered corner forces of an irregular voxel: in FP32 those of the voxel
+    // buffered corner forces of an irregular voxel.  With PF those of the voxel
     // one layer ahead are loaded a layer before they are used (24 more
-    // registers, which FP64 cannot spare), so their latency is hidden
-    constexpr bool PF = sizeof(T) == 4;
+    // registers); without it the FP32 kernel fits five waves per SIMD (86
+    // registers), which hides the load latency better
+    constexpr bool PF = false;
     T Fn[8][3];
     auto fetch_cut = [&](int mq) {
         const uint32_t q = (uint32_t)(-mq - 1);
