@@ -791,7 +791,8 @@ __global__ __launch_bounds__(1024) void k_fft_plane_inv(FftArgs A, const cpx<T> 
 // rows apart, so that the 16 columns x 2 rows of a half wave fall on 32
 // different banks in the staging and Green phases too.
 template <typename T, int N2, int TK>
-__global__ __launch_bounds__(512) void k_fft_z_t(FftArgs A, const cpx<T> *tw, const T *h0, const T *h1,
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 8 : 1)))
+void k_fft_z_t(FftArgs A, const cpx<T> *tw, const T *h0, const T *h1,
                                                   const T *h2, cpx<T> *spec, int64_t sz, int64_t sy, int nrhs,
                                                   EnrUpd<T> E) {
     static_assert(ENR_BLOCK == 512, "the enriched workgroups use the z-pass workgroup size");
@@ -1011,9 +1012,14 @@ template <typename T, int N2>
 static void zpass(const xfft_problem *p, FftArgs A, int nrhs, hipStream_t s, const Tables<T> &tb, cpx<T> *spec,
                   int64_t sz, int64_t sy, const EnrUpd<T> &E) {
     constexpr int TK = tkz_t<T>(N2);
-    const size_t lds = (size_t)3 * TK * lds_ls<3 * TK >= 32>(N2) * sizeof(cpx<T>);
+    // LDS holds the 3 tk lines a workgroup uses (tk <= TK columns share the nh
+    // columns evenly); at 128^3 in FP32 that is 13 of 16, which lets four
+    // workgroups share a CU (64 registers, eight waves per SIMD)
+    const int nh = p->g.nh, ntiles = (nh + TK - 1) / TK, tk = (nh + ntiles - 1) / ntiles;
+    const size_t line = (size_t)lds_ls<3 * TK >= 32>(N2) * sizeof(cpx<T>);
+    const size_t lds = (size_t)3 * tk * line;
     static bool init = false;
-    if (!init) { allow_lds(k_fft_z_t<T, N2, TK>, lds); init = true; }
+    if (!init) { allow_lds(k_fft_z_t<T, N2, TK>, (size_t)3 * TK * line); init = true; }
     const int64_t grid = ((int64_t)green_blocks<T>(p->g) + E.nblk) * nrhs;
     k_fft_z_t<T, N2, TK><<<(unsigned)grid, 512, lds, s>>>(A, tb.tws[2], tb.half[0], tb.half[1], tb.half[2], spec,
                                                         sz, sy, nrhs, E);
