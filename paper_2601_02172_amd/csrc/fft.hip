@@ -1047,7 +1047,7 @@ template <typename T, int N> static void xinv_t(const xfft_problem *p, FftArgs A
 }
 template <typename T, int N1, bool INV> static void ypass_t(const xfft_problem *p, FftArgs A, int nrhs,
                                                            hipStream_t s, const cpx<T> *tw, cpx<T> *spec) {
-    constexpr int TK = 16;
+    constexpr int TK = N1 >= 256 ? 8 : 16;
     const size_t lds = (size_t)TK * fft_ls(N1) * sizeof(cpx<T>);
     static bool init = false;
     if (!init) { allow_lds(k_fft_y_t<T, N1, TK, INV>, lds); init = true; }
