@@ -369,7 +369,7 @@ __global__ __launch_bounds__(256) void k_fft_x_inv(FftArgs A, FftPlan pl, const 
 // the LDS Stockham transform of fft_lines.h.  Spectrum layout [c][kz][ky][kx].
 template <int N> struct XCfg {
     static constexpr int NH = N / 2 + 1;
-    static constexpr int PP = 4096 / N;         // row pairs per workgroup
+    static constexpr int PP = (N >= 256 ? 2048 : 4096) / N;   // row pairs per workgroup
     static constexpr int LS = fft_ls(N);
 };
 
