@@ -20,6 +20,7 @@ Prints ONE JSON line.  ``--gpus`` above 1 is not supported (single-GPU build).
 
 import argparse
 import json
+import re
 import os
 import sys
 import time
@@ -45,14 +46,14 @@ REGULAR_OPS_PER_VOXEL = 36 + 6 * 12 + 18 + 48 + 24 + 3
 COPY_BYTES = 256 << 20
 # kernel classes -> substrings of the HIP kernel names
 KERNEL_NAMES = {
-    "regular_voxels": ["k_regular<"],
-    "irregular_voxels": ["k_irregular<"],
-    "enriched_gather": ["k_enriched<"],
-    "fft_x_forward": ["k_fft_plane_fwd<", "k_fft_x_fwd<"],
-    "fft_y_forward": ["k_fft_y<{t}, false>"],
-    "fft_z_green": ["k_fft_z_t<", "k_fft_z_green<"],
-    "fft_y_inverse": ["k_fft_y<{t}, true>"],
-    "fft_x_inverse": ["k_fft_plane_inv<", "k_fft_x_inv<"],
+    "regular_voxels": [r"k_regular<"],
+    "irregular_voxels": [r"k_irregular<"],
+    "enriched_gather": [r"k_enriched<"],
+    "fft_x_forward": [r"k_fft_plane_fwd<", r"k_fft_x_fwd(_t)?<"],
+    "fft_y_forward": [r"k_fft_y(_t)?<{t}(, \d+, \d+)?, false>"],
+    "fft_z_green": [r"k_fft_z_t<", r"k_fft_z_green<"],
+    "fft_y_inverse": [r"k_fft_y(_t)?<{t}(, \d+, \d+)?, true>"],
+    "fft_x_inverse": [r"k_fft_plane_inv<", r"k_fft_x_inv(_t)?<"],
 }
 
 
@@ -109,7 +110,7 @@ def _kernel_class(name):
         return None
     t = "float" if prec == "fp32" else "double"
     for k, pats in KERNEL_NAMES.items():
-        if any(p.format(t=t) in name for p in pats):
+        if any(re.search(p.replace("{t}", t), name) for p in pats):
             return k, prec
     return None
 
