@@ -97,6 +97,15 @@ def test_setup_rejects_invalid_scheme(scheme, precision):
                      o) == X.XFFT_EINVAL
 
 
+@pytest.mark.parametrize("disc", [2, -1])
+def test_setup_rejects_invalid_discretization(disc):
+    o = pkg.default_options()
+    assert o.discretization == 0
+    o.discretization = disc
+    assert _setup_rc([8, 8, 8], [8.0] * 3, np.ones(512), np.zeros(512, dtype=np.int32), np.array([[1.0, 0.5]]),
+                     o) == X.XFFT_EINVAL
+
+
 def test_setup_without_device_reports_device_error():
     import torch
     if torch.cuda.is_available():
