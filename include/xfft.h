@@ -17,7 +17,11 @@
  * Conventions shared by every entry point:
  *  - Grid n[3] nodes per axis (periodic; node (i,j,k) at (i,j,k)*h), cubic
  *    voxels h = len[0]/n[0] = len[1]/n[1] = len[2]/n[2].  Each n[k] must be
- *    even, >= 4 and of the form 2^a 3^b (FFT radices 2, 3, 4).
+ *    even, >= 4 and of the form 2^a 3^b (FFT radices 2, 3, 4), and its line
+ *    FFT must fit one workgroup: at most 1024 (x, y) or 2048 (z, three lines)
+ *    butterflies in its smallest-radix stage and 64 KiB of LDS.  Accepted:
+ *    every such length up to 1296 on all axes, and on x and y also 1458 to
+ *    2304, 2916 and 3072; other lengths give XFFT_EINVAL.
  *  - Nodal arrays have N = n0*n1*n2 entries at index i + n0*(j + n1*k).
  *  - Symmetric tensors are Voigt-Mandel 6-vectors (11, 22, 33, sqrt2*23,
  *    sqrt2*13, sqrt2*12); C_eff is the 6x6 Mandel matrix, row-major.
@@ -187,6 +191,15 @@ int xfft_apply_operator(xfft_problem *p, int32_t precision, const double *x,
                         const double *macro_strain, double *y, double *avg_stress);
 int xfft_apply_precond(xfft_problem *p, int32_t precision, const double *f,
                        double *y, double *res2);
+
+/* Voxel-average stress of a state (eq. Sapp_q per element, summed over the six
+ * elements of each voxel; voxel volume 1 in voxel units): stress[6][N] (Mandel,
+ * voxel index fastest) = sum_e in voxel int_e C (eps_bar + grad^s x), FP64.
+ * x[3N + 3nX] in the step-level layout, macro_strain NULL (zero) or [6].  The
+ * same kernels produce the stress output of xfft_solve.
+ * xfft_apply_operator runs the kernels without the stress integral when
+ * avg_stress is NULL (the variant of the CG iterations), with it otherwise. */
+int xfft_voxel_stress(xfft_problem *p, const double *x, const double *macro_strain, double *stress);
 
 /* Sizes and enriched-node data: info[0..5] = N, nX, irregular voxels, cut
  * elements, multi-label cut elements, nphase; jlist[nX] (NULL allowed) = node

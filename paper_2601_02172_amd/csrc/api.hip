@@ -671,6 +671,7 @@ int xfft_setup(const int32_t n[3], const double len[3], const double *levelset, 
     if (!n || !len || !levelset || !phase || !lame || nphase < 1) return XFFT_EINVAL;
     for (int a = 0; a < 3; ++a)
         if (!size_ok(n[a]) || !(len[a] > 0.0) || !std::isfinite(len[a])) return XFFT_EINVAL;
+    if (!fft_sizes_ok(n[0], n[1], n[2])) return XFFT_EINVAL;
     // the operator addresses the three components of a field of one load with
     // 32-bit byte offsets
     if ((int64_t)n[0] * n[1] * n[2] * 3 * (int64_t)sizeof(double) >= ((int64_t)1 << 32)) return XFFT_EINVAL;
@@ -786,24 +787,9 @@ int xfft_solve_device(xfft_problem *p, int32_t nload, const double *strain_dev, 
     if (stream) HIP_OK(hipStreamSynchronize((hipStream_t)stream));
     std::vector<double> strain(6 * nload);
     HIP_OK(hipMemcpy(strain.data(), strain_dev, sizeof(double) * 6 * nload, hipMemcpyDeviceToHost));
-    int rc = solve_impl(p, nload, strain.data(), nullptr, nullptr, avg_stress_dev, nullptr, stats, true);
-    if (rc < 0) return rc;
-    if (disp_dev) {
-        // copy and convert to units of len on the host side of a small staging pass
-        const size_t cnt = (size_t)3 * p->g.N;
-        std::vector<double> tmp(cnt);
-        for (int l = 0; l < nload; ++l) {
-            // the last solved block holds the final loads; re-read from the stored solutions when available
-            const double *src = nullptr;
-            if (p->sol_unit_basis) src = p->sol_u + cnt * l;
-            else if (nload == 1 || !p->batch) src = p->w64.u;      // single block
-            else src = p->w64.u + cnt * l;
-            HIP_OK(hipMemcpy(tmp.data(), src, sizeof(double) * cnt, hipMemcpyDeviceToHost));
-            for (double &v : tmp) v *= p->h;
-            HIP_OK(hipMemcpy(disp_dev + cnt * l, tmp.data(), sizeof(double) * cnt, hipMemcpyHostToDevice));
-        }
-    }
-    return rc;
+    // every solved block writes its loads' displacements (scaled to units of
+    // len on the device) straight into disp_dev
+    return solve_impl(p, nload, strain.data(), disp_dev, nullptr, avg_stress_dev, nullptr, stats, true);
 }
 
 int xfft_apply_operator(xfft_problem *p, int32_t precision, const double *x, const double *macro_strain, double *y,
@@ -827,7 +813,7 @@ int xfft_apply_operator(xfft_problem *p, int32_t precision, const double *x, con
         HIP_OK(hipMemcpyAsync(w.d, x, sizeof(double) * 3 * N, hipMemcpyHostToDevice, s));
         if (nX) HIP_OK(hipMemcpyAsync(w.de, x + 3 * N, sizeof(double) * 3 * nX, hipMemcpyHostToDevice, s));
         launch_operator<double>(p, w, p->t64, w.d, w.de, w.z, w.ze, macro_strain != nullptr, 1.0, 1, nullptr, 0,
-                                nullptr, s);
+                                nullptr, s, avg_stress != nullptr);
         launch_scalars(p, SC_SUM_ONLY, 0, 1, 0, sum_dev, s, true);
         HIP_OK(hipMemcpyAsync(y, w.z, sizeof(double) * 3 * N, hipMemcpyDeviceToHost, s));
         if (nX) HIP_OK(hipMemcpyAsync(y + 3 * N, w.ze, sizeof(double) * 3 * nX, hipMemcpyDeviceToHost, s));
@@ -837,8 +823,9 @@ int xfft_apply_operator(xfft_problem *p, int32_t precision, const double *x, con
         for (size_t q = 0; q < xf.size(); ++q) xf[q] = (float)x[q];
         HIP_OK(hipMemcpyAsync(w.d, xf.data(), sizeof(float) * 3 * N, hipMemcpyHostToDevice, s));
         if (nX) HIP_OK(hipMemcpyAsync(w.de, xf.data() + 3 * N, sizeof(float) * 3 * nX, hipMemcpyHostToDevice, s));
+        // without avg_stress the stress-free kernels run (those of the FP32 CG iterations)
         launch_operator<float>(p, w, p->t32, w.d, w.de, w.z, w.ze, macro_strain != nullptr, 1.0f, 1, nullptr, 0,
-                               nullptr, s);
+                               nullptr, s, avg_stress != nullptr);
         launch_scalars(p, SC_SUM_ONLY, 0, 1, 0, sum_dev, s, true);
         HIP_OK(hipMemcpyAsync(yf.data(), w.z, sizeof(float) * 3 * N, hipMemcpyDeviceToHost, s));
         if (nX) HIP_OK(hipMemcpyAsync(yf.data() + 3 * N, w.ze, sizeof(float) * 3 * nX, hipMemcpyDeviceToHost, s));
@@ -855,6 +842,36 @@ int xfft_apply_operator(xfft_problem *p, int32_t precision, const double *x, con
         avg_stress[3] = r2 * sum[4] / V; avg_stress[4] = r2 * sum[5] / V; avg_stress[5] = r2 * sum[6] / V;
     }
     return XFFT_OK;
+}
+
+int xfft_voxel_stress(xfft_problem *p, const double *x, const double *macro_strain, double *stress) {
+    if (!p || !x || !stress) return XFFT_EINVAL;
+    HIP_OK(hipSetDevice(p->device));
+    const int64_t N = p->g.N, nX = p->g.nX;
+    int rc = alloc_work<double>(p, p->w64, 1);
+    if (!rc) rc = ensure_state(p, 1);
+    if (rc) return rc;
+    double eb[6] = {0, 0, 0, 0, 0, 0};
+    if (macro_strain) std::memcpy(eb, macro_strain, sizeof(eb));
+    rc = reset_state(p, 1, eb);
+    if (rc) return rc;
+    hipStream_t s = p->stream;
+    double *vs = nullptr;
+    if (hipMalloc(&vs, sizeof(double) * 6 * N) != hipSuccess) return XFFT_ENOMEM;
+    Work<double> &w = p->w64;
+    rc = XFFT_OK;
+    if (hipMemcpyAsync(w.d, x, sizeof(double) * 3 * N, hipMemcpyHostToDevice, s) != hipSuccess ||
+        (nX && hipMemcpyAsync(w.de, x + 3 * N, sizeof(double) * 3 * nX, hipMemcpyHostToDevice, s) != hipSuccess))
+        rc = XFFT_EDEVICE;
+    if (!rc) {
+        launch_operator<double>(p, w, p->t64, w.d, w.de, w.z, w.ze, macro_strain != nullptr, 1.0, 1, nullptr, 0, vs,
+                                s, true);
+        if (hipMemcpyAsync(stress, vs, sizeof(double) * 6 * N, hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            rc = XFFT_EDEVICE;
+    }
+    (void)hipFree(vs);
+    return rc;
 }
 
 int xfft_apply_precond(xfft_problem *p, int32_t precision, const double *f, double *y, double *res2) {

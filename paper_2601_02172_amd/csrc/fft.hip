@@ -973,6 +973,38 @@ template <typename T> static bool plane_path(const Geometry &g) {
 // (about 50 KB, three workgroups per CU)
 template <typename T> static constexpr int tkz_t(int n2) { return (sizeof(T) == 8 ? 8 : 16) / (n2 >= 256 ? 2 : 1); }
 
+// The generic passes run every line of a workgroup through lds_fft, which
+// handles at most MAXB * threads butterflies per stage, and hold their lines
+// in at most 64 KiB of LDS.  A grid whose generic pass would exceed either
+// limit is rejected at setup.
+static bool ct_xy_size(int n) { return ztmpl_size(n); }
+static int min_radix(int n) {
+    const FftPlan pl = make_plan(n);
+    int r = 4;
+    for (int s = 0; s < pl.nstages; ++s) r = pl.radix[s] < r ? pl.radix[s] : r;
+    return r;
+}
+template <typename T> static bool generic_fits(int lines, int n, int threads) {
+    return (int64_t)lines * (n / min_radix(n)) <= (int64_t)MAXB * threads &&
+           (size_t)lines * (n + 1) * sizeof(cpx<T>) <= (size_t)65536;
+}
+template <typename T> static bool fft_fits(const Geometry &g) {
+    if (!plane_path<T>(g)) {
+        if (!ct_xy_size(g.n0) && !generic_fits<T>(pairs_for<T>(g.n0), g.n0, 256)) return false;
+        if (!ct_xy_size(g.n1) && !generic_fits<T>(tk_for<T>(g.n1, 1, 256), g.n1, 256)) return false;
+    }
+    if (!ztmpl_size(g.n2) && !generic_fits<T>(3 * tk_z(g), g.n2, 512)) return false;
+    return true;
+}
+bool fft_sizes_ok(int n0, int n1, int n2) {
+    Geometry g{};
+    g.n0 = n0; g.n1 = n1; g.n2 = n2; g.nh = n0 / 2 + 1;
+    g.N = (int64_t)n0 * n1 * n2;
+    for (int n : {n0, n1, n2})
+        if (make_plan(n).nstages < 0) return false;
+    return fft_fits<double>(g) && fft_fits<float>(g);
+}
+
 template <typename T> int green_blocks(const Geometry &g) {
     const int tk = ztmpl_size(g.n2) ? tkz_t<T>(g.n2) : tk_z(g);
     return g.n1 * ((g.nh + tk - 1) / tk);

@@ -9,6 +9,8 @@ SlotLayout slot_layout(const Geometry &g);
 // regular-voxel operator depth (planes per block); kz in {4, 8, 16}
 void set_depth(SlotLayout &L, const Geometry &g, int kz);
 int green_slots(const Geometry &g);
+// false when a line FFT of the grid would exceed what the generic passes handle
+bool fft_sizes_ok(int n0, int n1, int n2);
 template <typename T> int green_blocks(const Geometry &g);
 
 // Operator r(x) = A x + (macro-strain term) on up to nrhs right-hand sides.

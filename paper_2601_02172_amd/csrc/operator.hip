@@ -511,7 +511,9 @@ __device__ __forceinline__ void irregular_tet(const T (&Lc)[8], const T *__restr
     }
 }
 
-template <typename T, bool HX, bool EB>
+// ST: accumulate the stress integral (criterion 0 and output passes); without
+// it the partial-sum slots carry only the dot product, as in k_regular.
+template <typename T, bool HX, bool EB, bool ST>
 __global__ __launch_bounds__(128) void k_irregular(OpArgs<T> A) {
     __shared__ double red[2 * 7];
     const int64_t lb = xcd_remap(blockIdx.x, gridDim.x);
@@ -574,8 +576,10 @@ __global__ __launch_bounds__(128) void k_irregular(OpArgs<T> A) {
             elem(reinterpret_cast<V4 *>(cb), o) = V4{vf[4 * k4], vf[4 * k4 + 1], vf[4 * k4 + 2], vf[4 * k4 + 3]};
             elem(reinterpret_cast<V4 *>(cbe), o) = V4{ve[4 * k4], ve[4 * k4 + 1], ve[4 * k4 + 2], ve[4 * k4 + 3]};
         }
-        add_sym(acc7, S);
-        if (A.vstress) store_vstress(A.vstress + (int64_t)r * 6 * N, N, vox, S);
+        if constexpr (ST) {
+            add_sym(acc7, S);
+            if (A.vstress) store_vstress(A.vstress + (int64_t)r * 6 * N, N, vox, S);
+        }
     }
     block_sum<7>(acc7, red);
     if (threadIdx.x == 0) {
@@ -654,10 +658,11 @@ void launch_operator(xfft_problem *p, Work<T> &w, const Tables<T> &tb, const T *
         A.slot0 = L.cut0;
         dim3 grid((unsigned)L.cut_n * nrhs, 1);
         xfft_prof_mark(p, -1, s);
-        if (hx && use_ebar) k_irregular<T, true, true><<<grid, 128, 0, s>>>(A);
-        else if (hx) k_irregular<T, true, false><<<grid, 128, 0, s>>>(A);
-        else if (use_ebar) k_irregular<T, false, true><<<grid, 128, 0, s>>>(A);
-        else k_irregular<T, false, false><<<grid, 128, 0, s>>>(A);
+        if (hx && use_ebar) k_irregular<T, true, true, true><<<grid, 128, 0, s>>>(A);
+        else if (hx && stress) k_irregular<T, true, false, true><<<grid, 128, 0, s>>>(A);
+        else if (hx) k_irregular<T, true, false, false><<<grid, 128, 0, s>>>(A);
+        else if (use_ebar) k_irregular<T, false, true, true><<<grid, 128, 0, s>>>(A);
+        else k_irregular<T, false, false, false><<<grid, 128, 0, s>>>(A);
         xfft_prof_mark(p, K_IRREGULAR + (sizeof(T) == 8 ? K_COUNT : 0), s);
     }
     {

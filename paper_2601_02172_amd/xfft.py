@@ -62,7 +62,7 @@ class Stats(ctypes.Structure):
 
 EXPORTS = [
     "xfft_default_options", "xfft_setup", "xfft_solve", "xfft_solve_device", "xfft_set_lame",
-    "xfft_grad_lame", "xfft_batch_solve", "xfft_apply_operator", "xfft_apply_precond",
+    "xfft_grad_lame", "xfft_batch_solve", "xfft_apply_operator", "xfft_apply_precond", "xfft_voxel_stress",
     "xfft_get_layout", "xfft_profile", "xfft_profile_begin", "xfft_profile_end", "xfft_destroy",
     "xfft_strerror",
 ]
@@ -109,6 +109,8 @@ def _lib():
     lib.xfft_apply_operator.restype = ctypes.c_int
     lib.xfft_apply_precond.argtypes = [P, ctypes.c_int32, D, D, D]
     lib.xfft_apply_precond.restype = ctypes.c_int
+    lib.xfft_voxel_stress.argtypes = [P, D, D, D]
+    lib.xfft_voxel_stress.restype = ctypes.c_int
     lib.xfft_get_layout.argtypes = [P, I64, I64, D]
     lib.xfft_get_layout.restype = ctypes.c_int
     lib.xfft_profile.argtypes = [P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, D, I32]
@@ -175,6 +177,9 @@ class Problem:
         _check(lib.xfft_setup(_ip(n), _dp(length), _dp(L), _ip(ph), self.nphase, _dp(lame), ctypes.byref(o),
                               ctypes.byref(h)), "xfft_setup")
         self._h = h
+        # counts solves and moduli changes: the stored unit-load solutions that
+        # grad_lame uses belong to the current generation only
+        self.generation = 0
         info = self.layout(with_arrays=False)
         self.nX = info["nX"]
 
@@ -211,6 +216,7 @@ class Problem:
         st.iters = _ip(iters)
         st.outer_iters = _ip(outer)
         st.final_res = _dp(res)
+        self.generation += 1
         rc = _lib().xfft_solve(self._h, nl, _dp(E), _dp(d), _dp(s), _dp(avg), _dp(C), ctypes.byref(st))
         _check(rc, "xfft_solve", allow_not_converged=True)
         out.update(avg_stress=avg, iters=iters, outer_iters=outer, final_res=res, converged=(rc == XFFT_OK),
@@ -232,6 +238,7 @@ class Problem:
     def solve_device(self, strain_dev_ptr, nload, disp_dev_ptr=None, avg_dev_ptr=None, stream=None):
         """Device-pointer variant (pointers as ints, e.g. torch tensor.data_ptr())."""
         st = Stats()
+        self.generation += 1
         rc = _lib().xfft_solve_device(self._h, nload, ctypes.c_void_p(strain_dev_ptr),
                                       ctypes.c_void_p(disp_dev_ptr) if disp_dev_ptr else None,
                                       ctypes.c_void_p(avg_dev_ptr) if avg_dev_ptr else None,
@@ -242,6 +249,7 @@ class Problem:
         lame = np.ascontiguousarray(lame, dtype=np.float64).reshape(-1, 2)
         if lame.shape[0] != self.nphase:
             raise ValueError("wrong number of phases")
+        self.generation += 1
         _check(_lib().xfft_set_lame(self._h, _dp(lame)), "xfft_set_lame")
 
     def grad_lame(self, dL_dC):
@@ -252,16 +260,28 @@ class Problem:
         return g, dC
 
     # ------------------------------------------------------------------ step level
-    def apply_operator(self, x, macro_strain=None, precision="fp64"):
+    def apply_operator(self, x, macro_strain=None, precision="fp64", with_stress=True):
+        """y = r(x) and <sigma>; with_stress=False runs the stress-free kernels of the CG
+        iterations and returns avg = None."""
         x = np.ascontiguousarray(x, dtype=np.float64).ravel()
         if x.size != 3 * (self.N + self.nX):
             raise ValueError("x must have 3 (N + nX) entries")
         y = np.zeros_like(x)
-        avg = np.zeros(6)
+        avg = np.zeros(6) if with_stress else None
         E = None if macro_strain is None else np.ascontiguousarray(macro_strain, dtype=np.float64)
         _check(_lib().xfft_apply_operator(self._h, _PREC[precision], _dp(x), _dp(E), _dp(y), _dp(avg)),
                "xfft_apply_operator")
         return y, avg
+
+    def voxel_stress(self, x, macro_strain=None):
+        """Voxel-average Mandel stress (6, N) of the state x (FP64)."""
+        x = np.ascontiguousarray(x, dtype=np.float64).ravel()
+        if x.size != 3 * (self.N + self.nX):
+            raise ValueError("x must have 3 (N + nX) entries")
+        out = np.zeros((6, self.N))
+        E = None if macro_strain is None else np.ascontiguousarray(macro_strain, dtype=np.float64)
+        _check(_lib().xfft_voxel_stress(self._h, _dp(x), _dp(E), _dp(out)), "xfft_voxel_stress")
+        return out
 
     def apply_precond(self, f, precision="fp64"):
         f = np.ascontiguousarray(f, dtype=np.float64).ravel()
@@ -318,6 +338,8 @@ def batch_effective_stiffness(problems, with_stats=False):
     iters = np.zeros((len(problems), 6), dtype=np.int32)
     outer = np.zeros((len(problems), 6), dtype=np.int32)
     st = (Stats * len(problems))()
+    for p in problems:
+        p.generation += 1
     for i in range(len(problems)):
         st[i].iters = iters[i].ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
         st[i].outer_iters = outer[i].ctypes.data_as(ctypes.POINTER(ctypes.c_int32))

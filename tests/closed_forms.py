@@ -1,7 +1,7 @@
 """Textbook closed forms used as pins (none of them is the discretisation itself).
 
 * rank-one laminate of isotropic phases (traction continuity + strain
-  compatibility across planar interfaces);
+  compatibility across planar interfaces): phase stresses and C_eff;
 * composite-sphere bulk modulus (Hashin), the neutral-inclusion construction
   of the Hashin study;
 * dilute Eshelby estimates for spherical inclusions;
@@ -28,28 +28,39 @@ def iso_stiffness(lam, mu):
     return lam * np.outer(one, one) + 2.0 * mu * np.eye(6)
 
 
-def laminate_stiffness(normal, fractions, lames):
-    """Effective Mandel stiffness of a rank-one laminate of isotropic phases."""
+def laminate_phase_stresses(normal, fractions, lames, ebar):
+    """Uniform stress (Mandel) in each phase of a rank-one laminate under the macro strain ebar.
+
+    Each phase strain is ebar + sym(a_p (x) n) (compatibility across the
+    planes); the traction sigma_p n is the same vector t in every phase and the
+    jumps a_p average to zero over the fractions.
+    """
     n = np.asarray(normal, dtype=np.float64)
     n = n / np.linalg.norm(n)
+    eb = mandel_to_tensor(np.asarray(ebar, dtype=np.float64))
+    Kinv, rhs = [], []
+    for (lam, mu) in lames:
+        K = mu * np.eye(3) + (lam + mu) * np.outer(n, n)
+        sig = lam * np.trace(eb) * np.eye(3) + 2.0 * mu * eb
+        Kinv.append(np.linalg.inv(K))
+        rhs.append(np.linalg.inv(K) @ (sig @ n))
+    Kavg = sum(f * Ki for f, Ki in zip(fractions, Kinv))
+    t = np.linalg.solve(Kavg, sum(f * r for f, r in zip(fractions, rhs)))
+    out = []
+    for (lam, mu), Ki in zip(lames, Kinv):
+        sig0 = lam * np.trace(eb) * np.eye(3) + 2.0 * mu * eb
+        a = Ki @ (t - sig0 @ n)
+        eps = eb + 0.5 * (np.outer(a, n) + np.outer(n, a))
+        out.append(tensor_to_mandel(lam * np.trace(eps) * np.eye(3) + 2.0 * mu * eps))
+    return out
+
+
+def laminate_stiffness(normal, fractions, lames):
+    """Effective Mandel stiffness of a rank-one laminate of isotropic phases."""
     C = np.zeros((6, 6))
     for k in range(6):
-        eb = mandel_to_tensor(np.eye(6)[k])
-        Kinv, rhs = [], []
-        for (lam, mu) in lames:
-            K = mu * np.eye(3) + (lam + mu) * np.outer(n, n)
-            sig = lam * np.trace(eb) * np.eye(3) + 2.0 * mu * eb
-            Kinv.append(np.linalg.inv(K))
-            rhs.append(np.linalg.inv(K) @ (sig @ n))
-        Kavg = sum(f * Ki for f, Ki in zip(fractions, Kinv))
-        t = np.linalg.solve(Kavg, sum(f * r for f, r in zip(fractions, rhs)))
-        savg = np.zeros((3, 3))
-        for f, (lam, mu), Ki in zip(fractions, lames, Kinv):
-            sig0 = lam * np.trace(eb) * np.eye(3) + 2.0 * mu * eb
-            a = Ki @ (t - sig0 @ n)
-            eps = eb + 0.5 * (np.outer(a, n) + np.outer(n, a))
-            savg += f * (lam * np.trace(eps) * np.eye(3) + 2.0 * mu * eps)
-        C[:, k] = tensor_to_mandel(savg)
+        sig = laminate_phase_stresses(normal, fractions, lames, np.eye(6)[k])
+        C[:, k] = sum(f * s for f, s in zip(fractions, sig))
     return C
 
 

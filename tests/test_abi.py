@@ -52,7 +52,8 @@ def _setup_rc(n, length, L, ph, lame, opt=None):
     return rc
 
 
-@pytest.mark.parametrize("case", ["odd", "prime", "small", "noncubic", "nan", "phase", "mu", "bulk", "huge"])
+@pytest.mark.parametrize("case", ["odd", "prime", "small", "noncubic", "nan", "phase", "mu", "bulk", "huge",
+                                  "fft_z", "fft_x", "fft_y"])
 def test_setup_rejects_invalid_input(case):
     n = [8, 8, 8]
     length = [8.0, 8.0, 8.0]
@@ -79,6 +80,12 @@ def test_setup_rejects_invalid_input(case):
         lame = np.array([[1.0, 0.0]])
     elif case == "bulk":
         lame = np.array([[-1.0, 0.5]])
+    elif case in ("fft_z", "fft_x", "fft_y"):
+        # line FFTs beyond one workgroup of the generic passes: 3 x 1536 / 2
+        # butterflies along z, 2592 / 2 along x or y
+        n = {"fft_z": [16, 16, 1536], "fft_x": [2592, 16, 16], "fft_y": [16, 2592, 16]}[case]
+        length = [float(v) for v in n]
+        L = np.ones(int(np.prod(n))); ph = np.zeros(int(np.prod(n)), dtype=np.int32)
     elif case == "huge":
         # 3 N doubles of one load above 4 GiB: rejected before the level set is read
         n = [1024, 1024, 1024]

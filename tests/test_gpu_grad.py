@@ -116,3 +116,37 @@ def test_ellipsoid_rve_gradient_central_differences():
                 vals.append(np.sum((p.effective_stiffness()[0] - Ct) ** 2))
             fd = (vals[0] - vals[1]) / (2 * h)
             assert abs(fd - g[ph, j]) < 1e-5 * abs(g[ph, j]) + 1e-9 * np.abs(g).max(), (ph, j, fd, g[ph, j])
+
+
+def test_autograd_two_forwards_then_two_backwards():
+    # each graph node takes the gradient at the moduli of its own forward, even
+    # when another forward re-solved the problem in between
+    import torch
+    from paper_2601_02172_amd.torch_ops import effective_stiffness as ceff
+    lame_a = _case("sphere8")[3]
+    lame_b = lame_a * np.array([[1.3, 0.8], [0.7, 1.6]])
+    Ct = torch.eye(6, dtype=torch.float64)
+    ref = []
+    with _gpu("sphere8", rtol=1e-12) as p:
+        for lm in (lame_a, lame_b):
+            t = torch.tensor(lm, dtype=torch.float64, requires_grad=True)
+            ((ceff(t, p) - Ct) ** 2).sum().backward()
+            ref.append(t.grad.numpy().copy())
+        ta = torch.tensor(lame_a, dtype=torch.float64, requires_grad=True)
+        tb = torch.tensor(lame_b, dtype=torch.float64, requires_grad=True)
+        loss_a = ((ceff(ta, p) - Ct) ** 2).sum()
+        loss_b = ((ceff(tb, p) - Ct) ** 2).sum()
+        loss_a.backward()
+        loss_b.backward()
+    assert np.abs(ref[0] - ref[1]).max() > 1e-3 * np.abs(ref[0]).max()
+    np.testing.assert_allclose(ta.grad.numpy(), ref[0], rtol=1e-10, atol=1e-14)
+    np.testing.assert_allclose(tb.grad.numpy(), ref[1], rtol=1e-10, atol=1e-14)
+
+
+def test_autograd_raises_when_not_converged():
+    import torch
+    from paper_2601_02172_amd.torch_ops import effective_stiffness as ceff
+    with _gpu("sphere8", rtol=1e-12, maxit=2, use_graph=False) as p:
+        t = torch.tensor(_case("sphere8")[3], dtype=torch.float64, requires_grad=True)
+        with pytest.raises(RuntimeError, match="did not reach"):
+            ceff(t, p)

@@ -19,7 +19,7 @@ from microstructure.shapes import coated_sphere_levelset
 from oracle.xfem import Discretization
 from oracle.system import System
 from oracle.green import GreenOperator
-from oracle.homogenize import effective_stiffness
+from oracle.homogenize import effective_stiffness, solve_loads
 from closed_forms import laminate_stiffness
 
 pytestmark = pytest.mark.gpu
@@ -268,5 +268,76 @@ def test_spheres64_against_golden(precision, rtol, tol):
     with Problem(cfg["n"], cfg["length"], cfg["L"], cfg["phase"], cfg["lame"], rtol=rtol, precision=precision) as p:
         C, info = p.effective_stiffness()
         lay = p.layout(with_arrays=False)
+    assert lay["nX"] == g["stats"]["n_enriched"]
+    assert _rel(C, np.array(g["c_eff"])) < tol
+
+
+@pytest.mark.parametrize("name", STEP_CASES)
+def test_voxel_stress_matches_oracle(name):
+    # eq. Sapp_q per element, summed over each voxel: element by element
+    d, s = oracle_of(name)
+    rng = np.random.default_rng(17)
+    x = rng.standard_normal(d.ndof)
+    eb = rng.standard_normal(6)
+    with gpu_of(name) as p:
+        vs = p.voxel_stress(x, macro_strain=eb)
+        vs0 = p.voxel_stress(x)
+    ref = s.voxel_stress(x, eb)
+    ref0 = s.voxel_stress(x, np.zeros(6))
+    assert _rel(vs, ref) < 1e-12
+    assert _rel(vs0, ref0) < 1e-12
+
+
+def test_solve_stress_output_matches_oracle():
+    # the stress output of xfft_solve at the converged solution (GPU rtol 1e-12,
+    # oracle 1e-13), two loads, grid spacing h != 1 (stresses do not scale with h)
+    from paper_2601_02172_amd import Problem
+    name = "two_spheres_36x24x18"
+    d, s = oracle_of(name)
+    n, L, ph, lame = _case(name)
+    E = np.eye(6)[[0, 4]]
+    U, _ = solve_loads(d, E, tol=1e-13)
+    h = 0.3
+    with Problem(n, [v * h for v in n], L * h, ph, lame, rtol=1e-12) as p:
+        r = p.solve(E, stress=True)
+    for k in range(2):
+        ref = s.voxel_stress(U[k], E[k])
+        assert _rel(r["stress"][k], ref) < 1e-9
+        np.testing.assert_allclose(r["avg_stress"][k], s.average_stress(U[k], E[k]), rtol=0,
+                                   atol=1e-10 * np.abs(ref).max())
+
+
+def test_device_buffer_solve_one_load_at_a_time():
+    # batch = 0 with three loads that are not the unit basis: every load's
+    # displacement and average stress equal the host solve's
+    import torch
+    from paper_2601_02172_amd import Problem
+    n, L, ph, lame = _case("two_spheres_36x24x18")
+    h = 0.5
+    E = np.array([[1.0, 0.2, 0.0, 0.0, 0.0, 0.0], [0.0, 0.0, 0.0, 1.0, 0.0, 0.0], [0.1, 0.0, 0.7, 0.0, 0.3, 0.0]])
+    with Problem(n, [v * h for v in n], L * h, ph, lame, rtol=1e-11, batch=False) as p:
+        r = p.solve(E, disp=True)
+        dev = torch.device("cuda:0")
+        strain = torch.tensor(E, dtype=torch.float64, device=dev).contiguous()
+        disp = torch.full((3, 3, p.N), float("nan"), dtype=torch.float64, device=dev)
+        avg = torch.full((3, 6), float("nan"), dtype=torch.float64, device=dev)
+        torch.cuda.synchronize()
+        p.solve_device(strain.data_ptr(), 3, disp.data_ptr(), avg.data_ptr())
+        d_dev, a_dev = disp.cpu().numpy(), avg.cpu().numpy()
+    assert np.abs(r["disp"][0] - r["disp"][1]).max() > 1e-3 * np.abs(r["disp"]).max()
+    np.testing.assert_allclose(a_dev, r["avg_stress"], rtol=0, atol=1e-13 * np.abs(r["avg_stress"]).max())
+    np.testing.assert_allclose(d_dev, r["disp"], rtol=0, atol=1e-13 * np.abs(r["disp"]).max())
+
+
+@pytest.mark.parametrize("precision,rtol,tol", [("fp64", 1e-12, 1e-10), ("mixed", 1e-11, 1e-8)])
+def test_spheres128_against_golden(precision, rtol, tol):
+    # the benchmark workload (128^3, 40 spheres, six unit loads) against the oracle
+    g = _golden("spheres128")
+    cfg = ms.config_spheres128()
+    from paper_2601_02172_amd import Problem
+    with Problem(cfg["n"], cfg["length"], cfg["L"], cfg["phase"], cfg["lame"], rtol=rtol, precision=precision) as p:
+        C, info = p.effective_stiffness()
+        lay = p.layout(with_arrays=False)
+    assert info["converged"]
     assert lay["nX"] == g["stats"]["n_enriched"]
     assert _rel(C, np.array(g["c_eff"])) < tol

@@ -263,3 +263,64 @@ def test_lame_gradient_matches_central_differences():
             Cs.append(effective_stiffness(dd, method="dense")[0])
         fd = (Cs[0] - Cs[1]) / (2 * dl)
         assert np.abs(fd - g[p, q]).max() < 1e-6 * np.abs(g[p, q]).max() + 1e-9
+
+
+# --------------------------------------------------------------------------- voxel stresses (eq. Sapp_q per voxel)
+def test_voxel_stress_of_a_linear_field_in_homogeneous_material():
+    # u = A x on the nodes: every voxel that does not straddle the periodic
+    # seam sees the uniform strain sym(A), so its average stress is
+    # C (eps_bar + sym A); u = 0 and u = const give C eps_bar everywhere
+    n = (5, 6, 4)
+    N = 120
+    lam, mu = 1.3, 0.7
+    d = Discretization(n, (5.0, 6.0, 4.0), np.ones(N), np.zeros(N, dtype=int), np.array([[lam, mu]]))
+    s = System(d)
+    C = iso_C(lam, mu)
+    rng = np.random.default_rng(4)
+    eb = rng.standard_normal(6)
+    for u in (np.zeros(d.ndof), np.repeat(rng.standard_normal(3), N)):
+        vs = s.voxel_stress(u, eb)
+        np.testing.assert_allclose(vs, np.tile((C @ eb)[:, None], (1, N)), rtol=0, atol=1e-14)
+    A = rng.standard_normal((3, 3))
+    i, j, k = np.meshgrid(np.arange(n[0]), np.arange(n[1]), np.arange(n[2]), indexing="ij")
+    xyz = np.stack([i.transpose(2, 1, 0).ravel(), j.transpose(2, 1, 0).ravel(), k.transpose(2, 1, 0).ravel()])
+    u = (A @ xyz).reshape(-1)                        # component-major, node index x fastest
+    vs = s.voxel_stress(u, eb)
+    E = 0.5 * (A + A.T)
+    e_lin = np.array([E[0, 0], E[1, 1], E[2, 2], np.sqrt(2) * E[1, 2], np.sqrt(2) * E[0, 2], np.sqrt(2) * E[0, 1]])
+    inner = ((xyz[0] < n[0] - 1) & (xyz[1] < n[1] - 1) & (xyz[2] < n[2] - 1))
+    assert inner.sum() == 4 * 5 * 3
+    np.testing.assert_allclose(vs[:, inner], np.tile((C @ (eb + e_lin))[:, None], (1, inner.sum())),
+                               rtol=0, atol=1e-13 * np.abs(C @ (eb + e_lin)).max())
+    assert np.abs(vs[:, ~inner] - (C @ (eb + e_lin))[:, None]).max() > 1e-3
+
+
+@pytest.mark.parametrize("load", [0, 5])
+def test_voxel_stress_of_laminate_matches_phase_stresses(load):
+    # face-aligned laminate, layer 1 at x in [1.37, 5.37): voxels wholly inside a
+    # layer carry that phase's closed-form stress, the two cut voxel columns the
+    # volume-weighted mix of both (fractions 0.63 / 0.37)
+    from closed_forms import laminate_phase_stresses
+    N, s1, w = 8, 1.37, 4.0
+    n = (N, N, N)
+    lame = np.array([[0.5769231, 0.3846154], [27.77778, 41.66667]])
+    L, ph = ms.laminate_levelset(n, (1, 0, 0), s1, s1 + w)
+    d = Discretization(n, (float(N),) * 3, L, ph, lame, keep_qp=False)
+    eb = np.eye(6)[load]
+    U, _ = solve_loads(d, eb, tol=1e-13)
+    vs = System(d).voxel_stress(U[0], eb)
+    sig0, sig1 = laminate_phase_stresses((1, 0, 0), [1.0 - w / N, w / N], lame, eb)
+    ix = np.arange(N ** 3) % N
+    frac1 = np.clip(np.minimum(ix + 1.0, s1 + w) - np.maximum(ix * 1.0, s1), 0.0, 1.0)
+    expect = np.outer(sig1, frac1) + np.outer(sig0, 1.0 - frac1)
+    assert sorted(set(np.round(frac1, 6))) == [0.0, 0.37, 0.63, 1.0]
+    np.testing.assert_allclose(vs, expect, rtol=0, atol=1e-10 * np.abs(expect).max())
+
+
+def test_voxel_stresses_average_to_the_average_stress(sphere8):
+    d = sphere8[0]
+    s = System(d)
+    rng = np.random.default_rng(9)
+    x = rng.standard_normal(d.ndof)
+    eb = rng.standard_normal(6)
+    np.testing.assert_allclose(s.voxel_stress(x, eb).mean(axis=1), s.average_stress(x, eb), rtol=1e-13, atol=1e-14)
