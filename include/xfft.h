@@ -201,6 +201,24 @@ int xfft_apply_precond(xfft_problem *p, int32_t precision, const double *f,
  * avg_stress is NULL (the variant of the CG iterations), with it otherwise. */
 int xfft_voxel_stress(xfft_problem *p, const double *x, const double *macro_strain, double *stress);
 
+/* Allocation-free variant of xfft_apply_operator, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops).
+ * FP64 only, device pointers: x_dev[3N + 3nX] (step-level layout, voxel
+ * units), macro_strain_dev NULL (zero) or [6], y_dev[3N + 3nX] receives
+ * r(x) (eq. resVector), avg_stress_dev NULL or [6] receives <sigma>.  Runs on
+ * `stream` (hipStream_t; NULL = the problem's stream) without waiting for it;
+ * the outputs are ready when the stream reaches this point.  The per-workgroup
+ * partial sums and the corner-force buffer of the irregular voxels live in a
+ * static 64 MiB device array per GPU (held until the process ends), so the call
+ * makes no allocation; grids needing more (8 NPART nslots + 384 x irregular
+ * voxels bytes, about 150 k irregular voxels) give XFFT_EINVAL, as does a call
+ * between xfft_profile_begin and xfft_profile_end.  All calls on one GPU share
+ * that array: calls that overlap in time on one GPU (other streams, other
+ * threads, other problems) race and must be serialised by the caller.
+ * Returns OK, EINVAL or EDEVICE (launch failure). */
+int xfft_apply_operator_noalloc(xfft_problem *p, const double *x_dev, const double *macro_strain_dev,
+                                double *y_dev, double *avg_stress_dev, void *stream);
+
 /* Sizes and enriched-node data: info[0..5] = N, nX, irregular voxels, cut
  * elements, multi-label cut elements, nphase; jlist[nX] (NULL allowed) = node
  * index of each enriched node; d0[nX] (NULL allowed) = D0_jj. */

@@ -14,7 +14,7 @@ ROOT = os.path.dirname(HERE)
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libxfft.so")
 
-SOURCES = ["setup.hip", "operator.hip", "fft.hip", "cg.hip", "grad.hip", "api.hip"]
+SOURCES = ["setup.hip", "operator.hip", "fft.hip", "cg.hip", "grad.hip", "api.hip", "noalloc.hip"]
 ARCH = "gfx950"
 
 

@@ -698,6 +698,8 @@ int xfft_setup(const int32_t n[3], const double len[3], const double *levelset, 
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1 || opt.device < 0 || opt.device >= ndev)
         return XFFT_EDEVICE;
     if (hipSetDevice(opt.device) != hipSuccess) return XFFT_EDEVICE;
+    // address of this device's work space of xfft_apply_operator_noalloc
+    if (static_scratch_init(opt.device) != XFFT_OK) return XFFT_EDEVICE;
     xfft_problem *p = new (std::nothrow) xfft_problem();
     if (!p) return XFFT_ENOMEM;
     p->device = opt.device;

@@ -22,6 +22,18 @@ void launch_operator(xfft_problem *p, Work<T> &w, const Tables<T> &tb, const T *
                      bool use_ebar, T sign, int nrhs, const Flags *flags, int parity, double *vstress,
                      hipStream_t s, bool stress = true);
 
+// The same with explicit work space: macro strains ebar[nrhs][6] (device),
+// corner-force buffer cutbuf (48 cut_rows(nirr) values per right-hand side)
+// and partial-sum slots partial (nslots NPART doubles per right-hand side).
+template <typename T>
+void launch_operator_ws(xfft_problem *p, const Tables<T> &tb, const T *x, const T *xe, T *y, T *ye,
+                        const double *ebar, bool use_ebar, T sign, int nrhs, const Flags *flags, int parity,
+                        double *vstress, hipStream_t s, bool stress, T *cutbuf, double *partial);
+
+// Allocation-free entry point: looks up this device's static scratch area
+// (once per device; call with the device current).  0 or XFFT_EDEVICE.
+int static_scratch_init(int device);
+
 // Green operator passes.  mode_x_fwd: the residual update f -= alpha z is fused
 // when z is non-null.  The z pass writes the Parseval partials.  The enriched
 // residual update of launch_enr_update (mode enr_mode, output enr_out) follows

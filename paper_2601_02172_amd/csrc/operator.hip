@@ -634,18 +634,18 @@ __device__ __forceinline__ void enriched_block(const OpArgs<T> &A, int r, int bl
 }  // namespace
 
 template <typename T>
-void launch_operator(xfft_problem *p, Work<T> &w, const Tables<T> &tb, const T *x, const T *xe, T *y, T *ye,
-                     bool use_ebar, T sign, int nrhs, const Flags *flags, int parity, double *vstress,
-                     hipStream_t s, bool stress) {
+void launch_operator_ws(xfft_problem *p, const Tables<T> &tb, const T *x, const T *xe, T *y, T *ye,
+                        const double *ebar, bool use_ebar, T sign, int nrhs, const Flags *flags, int parity,
+                        double *vstress, hipStream_t s, bool stress, T *cutbuf, double *partial) {
     const Geometry &g = p->g;
     const SlotLayout &L = p->slots;
     OpArgs<T> A;
     A.x = x; A.xe = xe; A.y = y; A.ye = ye;
-    A.ebar = p->ebar; A.sign = sign; A.flags = flags; A.parity = parity;
+    A.ebar = ebar; A.sign = sign; A.flags = flags; A.parity = parity;
     A.vmat = p->vmat; A.irr = p->irr; A.irr_j = p->irr_j; A.irr_lab = p->irr_lab; A.jlist = p->jlist;
     A.enr_src = p->enr_src;
     A.irr_L = tb.irr_L; A.irr_M = tb.irr_M; A.d0is = tb.d0is; A.lame = tb.lame;
-    A.cutbuf = w.cutbuf; A.partial = p->partial; A.nslots = p->nslots;
+    A.cutbuf = cutbuf; A.partial = partial; A.nslots = p->nslots;
     A.vstress = vstress;
     A.n0 = g.n0; A.n1 = g.n1; A.n2 = g.n2; A.N = g.N; A.nX = g.nX; A.nirr = g.nirr;
     A.kz = L.kz; A.tiles_x = L.tiles_x;
@@ -679,6 +679,17 @@ void launch_operator(xfft_problem *p, Work<T> &w, const Tables<T> &tb, const T *
     }
 }
 
+template <typename T>
+void launch_operator(xfft_problem *p, Work<T> &w, const Tables<T> &tb, const T *x, const T *xe, T *y, T *ye,
+                     bool use_ebar, T sign, int nrhs, const Flags *flags, int parity, double *vstress,
+                     hipStream_t s, bool stress) {
+    launch_operator_ws<T>(p, tb, x, xe, y, ye, p->ebar, use_ebar, sign, nrhs, flags, parity, vstress, s, stress,
+                          w.cutbuf, p->partial);
+}
+
+template void launch_operator_ws<double>(xfft_problem *, const Tables<double> &, const double *, const double *,
+                                         double *, double *, const double *, bool, double, int, const Flags *, int,
+                                         double *, hipStream_t, bool, double *, double *);
 template void launch_operator<double>(xfft_problem *, Work<double> &, const Tables<double> &, const double *,
                                       const double *, double *, double *, bool, double, int, const Flags *, int,
                                       double *, hipStream_t, bool);

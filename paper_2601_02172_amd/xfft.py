@@ -63,7 +63,8 @@ class Stats(ctypes.Structure):
 EXPORTS = [
     "xfft_default_options", "xfft_setup", "xfft_solve", "xfft_solve_device", "xfft_set_lame",
     "xfft_grad_lame", "xfft_batch_solve", "xfft_apply_operator", "xfft_apply_precond", "xfft_voxel_stress",
-    "xfft_get_layout", "xfft_profile", "xfft_profile_begin", "xfft_profile_end", "xfft_destroy",
+    "xfft_apply_operator_noalloc", "xfft_get_layout", "xfft_profile", "xfft_profile_begin", "xfft_profile_end",
+    "xfft_destroy",
     "xfft_strerror",
 ]
 
@@ -109,6 +110,8 @@ def _lib():
     lib.xfft_apply_operator.restype = ctypes.c_int
     lib.xfft_apply_precond.argtypes = [P, ctypes.c_int32, D, D, D]
     lib.xfft_apply_precond.restype = ctypes.c_int
+    lib.xfft_apply_operator_noalloc.argtypes = [P, V, V, V, V, V]
+    lib.xfft_apply_operator_noalloc.restype = ctypes.c_int
     lib.xfft_voxel_stress.argtypes = [P, D, D, D]
     lib.xfft_voxel_stress.restype = ctypes.c_int
     lib.xfft_get_layout.argtypes = [P, I64, I64, D]
@@ -272,6 +275,16 @@ class Problem:
         _check(_lib().xfft_apply_operator(self._h, _PREC[precision], _dp(x), _dp(E), _dp(y), _dp(avg)),
                "xfft_apply_operator")
         return y, avg
+
+    def apply_operator_noalloc(self, x_dev_ptr, y_dev_ptr, macro_strain_dev_ptr=None, avg_dev_ptr=None,
+                               stream=None):
+        """xfft_apply_operator_noalloc on device pointers (ints, e.g. tensor.data_ptr()); FP64.
+
+        Enqueued on ``stream`` (or the problem's stream) without waiting for it."""
+        vp = lambda v: ctypes.c_void_p(v) if v else None
+        rc = _lib().xfft_apply_operator_noalloc(self._h, vp(x_dev_ptr), vp(macro_strain_dev_ptr), vp(y_dev_ptr),
+                                                vp(avg_dev_ptr), vp(stream))
+        return _check(rc, "xfft_apply_operator_noalloc")
 
     def voxel_stress(self, x, macro_strain=None):
         """Voxel-average Mandel stress (6, N) of the state x (FP64)."""
