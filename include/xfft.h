@@ -99,6 +99,13 @@ typedef struct {
     int32_t scheme;     /* XFFT_LCG (default), XFFT_NLCG, XFFT_BB or XFFT_BASIC; schemes other than
                            XFFT_LCG need precision XFFT_FP64 */
     int32_t discretization; /* XFFT_XFEM (default) or XFFT_P1 */
+    int32_t voxel_matrices; /* cached voxel matrices of the irregular voxels (Sec. 3, caching strategy): the
+                               scaled 48 x 48 matrix of each irregular voxel (FP64, and FP32 rounded once) replaces
+                               the moment form in the CG iterations (up to 6 loads per launch), read once for all
+                               loads: -1 (default) the faster of the two, timed at the first solve per precision;
+                               0 never; 1 always (also for xfft_apply_operator).  Costs 11.8 KB (FP64) / 5.9 KB
+                               (FP32) of device memory per irregular voxel; falls back to the moment form when the
+                               allocation fails.  Rebuilt after xfft_set_lame. */
 } xfft_options;
 
 typedef struct {
@@ -111,6 +118,7 @@ typedef struct {
     int64_t n_irregular_voxels; /* voxels with a cut element or mixed element materials */
     int64_t n_cut_elements;
     int64_t n_multilabel;  /* cut elements whose vertices on one side carry different labels */
+    int32_t voxel_matrices;/* 1 if the CG iterations of the last solve used the cached voxel matrices */
 } xfft_stats;
 
 /* Fill *opt with the defaults listed above. */

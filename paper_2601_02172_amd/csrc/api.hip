@@ -263,6 +263,71 @@ int autotune_depth(xfft_problem *p, Work<T> &w, const Tables<T> &tb, int nrhs) {
     return XFFT_OK;
 }
 
+// Cached voxel matrices for the CG iterations of precision T in the launch
+// configuration (nrhs, stress integral on or off): never, always, or -- the
+// default -- whichever of the moment form and the cached matrices applies the
+// operator faster, timed once per precision; the tables are (re)built for the
+// current moduli when used.  Allocation failure falls back to the moment form.
+template <typename T>
+int ensure_voxel_matrices(xfft_problem *p, Work<T> &w, const Tables<T> &tb, int nrhs, bool stress) {
+    const int pi = sizeof(T) == 8 ? 1 : 0;
+    if (p->g.nirr == 0 || p->vm_mode == 0 || nrhs > VM_MAXR) {
+        if (p->vm_on[pi]) drop_graph(p);
+        p->vm_on[pi] = false;
+        return XFFT_OK;
+    }
+    auto have = [&]() { return p->vm_valid && (pi ? p->vm64 != nullptr : p->vm32 != nullptr); };
+    auto build = [&]() -> int {
+        const int r = build_voxel_matrices(p, pi == 0 || p->vm32 != nullptr, pi == 1 || p->vm64 != nullptr);
+        return r == -3 ? XFFT_EDEVICE : r;       // -2: not enough memory, use the moment form
+    };
+    if (p->vm_mode == 1 || p->vm_tuned[pi]) {
+        const bool want = p->vm_mode == 1 || p->vm_on[pi];
+        if (want && !have()) {
+            const int r = build();
+            if (r == XFFT_EDEVICE) return r;
+            if (r) { p->vm_on[pi] = false; drop_graph(p); return XFFT_OK; }
+        }
+        if (p->vm_on[pi] != want) drop_graph(p);
+        p->vm_on[pi] = want;
+        return XFFT_OK;
+    }
+    if (!have()) {
+        const int r = build();
+        if (r == XFFT_EDEVICE) return r;
+        if (r) { p->vm_on[pi] = false; p->vm_tuned[pi] = true; return XFFT_OK; }
+    }
+    hipStream_t s = p->stream;
+    HIP_OK(hipMemsetAsync(w.d, 0, sizeof(T) * 3 * p->g.N * nrhs, s));
+    if (p->g.nX) HIP_OK(hipMemsetAsync(w.de, 0, sizeof(T) * 3 * p->g.nX * nrhs, s));
+    hipEvent_t e0, e1;
+    HIP_OK(hipEventCreate(&e0));
+    HIP_OK(hipEventCreate(&e1));
+    float best_ms[2] = {1e30f, 1e30f};
+    for (int mode = 0; mode < 2; ++mode) {
+        p->vm_on[pi] = mode == 1;
+        launch_operator<T>(p, w, tb, w.d, w.de, w.z, w.ze, false, (T)1, nrhs, nullptr, 0, nullptr, s, stress);
+        (void)hipEventRecord(e0, s);
+        for (int rep = 0; rep < 10; ++rep)
+            launch_operator<T>(p, w, tb, w.d, w.de, w.z, w.ze, false, (T)1, nrhs, nullptr, 0, nullptr, s, stress);
+        (void)hipEventRecord(e1, s);
+        float ms = 0.0f;
+        if (hipEventSynchronize(e1) == hipSuccess && hipEventElapsedTime(&ms, e0, e1) == hipSuccess) best_ms[mode] = ms;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    p->vm_on[pi] = best_ms[1] < best_ms[0];
+    p->vm_tuned[pi] = true;
+    if (!p->vm_on[pi]) {
+        // keep only tables some precision uses
+        if (pi == 0 && p->vm32) { (void)hipFree(p->vm32); p->vm32 = nullptr; }
+        if (pi == 1 && p->vm64 && !p->vm_on[0]) { (void)hipFree(p->vm64); p->vm64 = nullptr; }
+        if (!p->vm32 && !p->vm64) p->vm_valid = false;
+    }
+    drop_graph(p);
+    return XFFT_OK;
+}
+
 // Average stress (Mandel) of the FP64 iterate in w64.u for every rhs; optional voxel stress.
 // <sigma> (and voxel stresses when vstress_dev is set) of the FP64 iterate.
 // sigma_ready: the scalars already hold the exact <sigma> of that iterate (the
@@ -312,6 +377,11 @@ int solve_block(xfft_problem *p, int nrhs, const double *ebar_host, std::vector<
         p->tuned = true;
         drop_graph(p);
     }
+    // the CG iterations: FP32 without the stress integral inside the refinement,
+    // FP64 with it (criterion 0 tracks <sigma>)
+    rc = (p->precision == XFFT_MIXED) ? ensure_voxel_matrices<float>(p, p->w32, p->t32, nrhs, false)
+                                      : ensure_voxel_matrices<double>(p, p->w64, p->t64, nrhs, true);
+    if (rc) return rc;
     rc = reset_state(p, nrhs, ebar_host);
     if (rc) return rc;
     hipStream_t s = p->stream;
@@ -493,6 +563,7 @@ int solve_impl(xfft_problem *p, int nload, const double *strain, double *disp, d
         stats->n_irregular_voxels = p->g.nirr;
         stats->n_cut_elements = p->n_cut_elements;
         stats->n_multilabel = p->n_multilabel;
+        stats->voxel_matrices = p->vm_on[p->precision == XFFT_MIXED ? 0 : 1] ? 1 : 0;
     }
     return status;
 }
@@ -624,6 +695,7 @@ void xfft_default_options(xfft_options *opt) {
     opt->stream = nullptr;
     opt->scheme = XFFT_LCG;
     opt->discretization = XFFT_XFEM;
+    opt->voxel_matrices = -1;
 }
 
 const char *xfft_strerror(int code) {
@@ -656,6 +728,7 @@ void xfft_destroy(xfft_problem *p) {
         if (p->t32.half[a]) (void)hipFree(p->t32.half[a]);
     }
     drop_graph(p);
+    free_voxel_matrices(p);
     free_work(p->w64);
     free_work(p->w32);
     for (hipEvent_t e : p->prof_pool) (void)hipEventDestroy(e);
@@ -691,7 +764,8 @@ int xfft_setup(const int32_t n[3], const double len[3], const double *levelset, 
         !(opt.inner_rtol > 0.0 && opt.inner_rtol < 1.0) ||
         (opt.precision != XFFT_FP64 && opt.precision != XFFT_MIXED) || opt.scheme < XFFT_LCG ||
         opt.scheme > XFFT_BASIC || (opt.scheme != XFFT_LCG && opt.precision != XFFT_FP64) ||
-        (opt.discretization != XFFT_XFEM && opt.discretization != XFFT_P1))
+        (opt.discretization != XFFT_XFEM && opt.discretization != XFFT_P1) || opt.voxel_matrices < -1 ||
+        opt.voxel_matrices > 1)
         return XFFT_EINVAL;
     const double t0 = now_s();
     int ndev = 0;
@@ -716,6 +790,7 @@ int xfft_setup(const int32_t n[3], const double len[3], const double *levelset, 
     p->autotune = opt.autotune != 0;
     p->scheme = opt.scheme;
     p->p1 = opt.discretization == XFFT_P1 ? 1 : 0;
+    p->vm_mode = opt.voxel_matrices;
     if (opt.stream) {
         p->stream = (hipStream_t)opt.stream;
     } else {
@@ -774,6 +849,7 @@ int xfft_set_lame(xfft_problem *p, const double *lame) {
     HIP_OK(hipMemcpyAsync(p->t32.lame, l32.data(), sizeof(float) * 2 * p->g.nphase, hipMemcpyHostToDevice, p->stream));
     HIP_OK(hipStreamSynchronize(p->stream));
     p->sol_unit_basis = false;
+    p->vm_valid = false;          // cached voxel matrices depend on the moduli: rebuilt when next used
     return XFFT_OK;
 }
 
@@ -802,6 +878,11 @@ int xfft_apply_operator(xfft_problem *p, int32_t precision, const double *x, con
     int rc = alloc_work<double>(p, p->w64, 1);
     if (!rc && precision == XFFT_FP32) rc = alloc_work<float>(p, p->w32, 1);
     if (!rc) rc = ensure_state(p, 1);
+    if (rc) return rc;
+    // with the option "always" the step-level operator runs the cached voxel matrices too
+    if (p->vm_mode == 1)
+        rc = precision == XFFT_FP64 ? ensure_voxel_matrices<double>(p, p->w64, p->t64, 1, avg_stress != nullptr)
+                                    : ensure_voxel_matrices<float>(p, p->w32, p->t32, 1, avg_stress != nullptr);
     if (rc) return rc;
     double eb[6] = {0, 0, 0, 0, 0, 0};
     if (macro_strain) std::memcpy(eb, macro_strain, sizeof(eb));
@@ -980,6 +1061,8 @@ int xfft_batch_solve(xfft_problem *const *ps, int32_t nprob, double *c_eff, xfft
             rc = mixed ? autotune_depth<float>(p, p->w32, p->t32, nl) : autotune_depth<double>(p, p->w64, p->t64, nl);
             p->tuned = true;
         }
+        if (!rc) rc = mixed ? ensure_voxel_matrices<float>(p, p->w32, p->t32, nl, false)
+                            : ensure_voxel_matrices<double>(p, p->w64, p->t64, nl, true);
         if (!rc) rc = reset_state(p, nl, E);
         if (rc) return rc;
         HIP_OK(hipMemsetAsync(p->w64.u, 0, sizeof(double) * 3 * p->g.N * nl, p->stream));
@@ -1126,6 +1209,7 @@ int xfft_batch_solve(xfft_problem *const *ps, int32_t nprob, double *c_eff, xfft
             st.n_cut_elements = p->n_cut_elements;
             st.n_multilabel = p->n_multilabel;
             st.seconds_setup = p->seconds_setup;
+            st.voxel_matrices = p->vm_on[mixed ? 0 : 1] ? 1 : 0;
         }
     }
     if (rc) return rc;

@@ -171,8 +171,10 @@ void launch_scalars(xfft_problem *p, int op, int crit, int nrhs, int parity, dou
     if (op == SC_INIT_SIGMA || op == SC_ALPHA || op == SC_SUM_ONLY) {
         A.s0 = L.fe0;
         A.n = L.fe_n;
-        A.s1 = L.cut0;
-        A.n1 = L.cut_n + L.enr_n;
+        // irregular-voxel slots of the kernel the last operator launch used
+        // (moment form: before the enriched ones; cached matrices: after them)
+        A.s1 = p->last_op_vm ? L.enr0 : L.cut0;
+        A.n1 = p->last_op_vm ? L.enr_n + L.vm_n : L.cut_n + L.enr_n;
     } else {
         A.s0 = L.grn0;
         A.n = fp64 ? green_blocks<double>(p->g) : green_blocks<float>(p->g);

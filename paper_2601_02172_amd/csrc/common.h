@@ -136,12 +136,26 @@ template <typename T> struct Work {
 // irregular voxels rounded up to whole groups of 64 (corner-force buffer)
 __host__ __device__ inline int64_t cut_rows(int64_t nirr) { return (nirr + 63) & ~(int64_t)63; }
 
+// Cached voxel matrices (Sec. 3, caching strategy): per irregular voxel the
+// scaled 48 x 48 element matrix of the voxel (8 corners x (3 FE + 3 scaled
+// enriched dofs), symmetric) as its packed upper triangle, row a holding
+// columns a..47 at vm_row(a) + b, then six rows of 48 giving the voxel's stress
+// integral (tensor components xx, yy, zz, yz, xz, xy) per unit dof.
+constexpr int VM_K = 1176;        // packed upper triangle
+constexpr int VM_KP = 1184;       // start of the stress rows (padded to 16 values)
+constexpr int VM_STRIDE = 1472;   // values per voxel
+constexpr int VM_VPW = 4;         // voxels per wave of the cached-matrix kernel
+constexpr int VM_VPB = 4 * VM_VPW;// voxels per 256-thread workgroup
+constexpr int VM_MAXR = 6;        // loads per launch of the cached-matrix kernel
+__host__ __device__ constexpr int vm_row(int a) { return 47 * a - a * (a - 1) / 2; }
+
 // Partial-sum slot layout per right-hand side.
 struct SlotLayout {
     int fe0, fe_n;      // regular-voxel operator blocks at the current depth kz
     int fe_cap;         // slots reserved for the regular-voxel blocks (depth 4)
-    int cut0, cut_n;    // irregular-voxel blocks
+    int cut0, cut_n;    // irregular-voxel blocks (moment form)
     int enr0, enr_n;    // enriched gather blocks
+    int vm0, vm_n;      // irregular-voxel blocks of the cached voxel matrices (right after the enriched ones)
     int grn0, grn_n;    // Green (z pass) blocks
     int eu0, eu_n;      // enriched residual blocks
     int total;
@@ -233,6 +247,16 @@ struct xfft_problem {
     const void *graph_ptrs[3] = {nullptr, nullptr, nullptr};
     bool autotune = true;
     bool tuned = false;
+    // cached voxel matrices: option (-1 autotuned, 0 never, 1 always), the
+    // tables of each precision (built for the current moduli) and whether the
+    // CG iterations of that precision use them
+    int vm_mode = -1;
+    double *vm64 = nullptr;
+    float *vm32 = nullptr;
+    bool vm_valid = false;     // tables match the current moduli
+    bool vm_on[2] = {false, false};   // [0] FP32, [1] FP64
+    bool vm_tuned[2] = {false, false};
+    bool last_op_vm = false;   // the last operator launch used the cached matrices
     // profiling hook: events recorded before (id -1) and after (kernel id) every launch
     bool prof_on = false;
     std::vector<hipEvent_t> prof_pool;   // reusable events

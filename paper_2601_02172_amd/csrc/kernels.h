@@ -25,10 +25,16 @@ void launch_operator(xfft_problem *p, Work<T> &w, const Tables<T> &tb, const T *
 // The same with explicit work space: macro strains ebar[nrhs][6] (device),
 // corner-force buffer cutbuf (48 cut_rows(nirr) values per right-hand side)
 // and partial-sum slots partial (nslots NPART doubles per right-hand side).
+// allow_vm: the cached voxel matrices may replace the moment form (CG
+// iterations); their partial sums then go to the slots after the enriched ones.
 template <typename T>
 void launch_operator_ws(xfft_problem *p, const Tables<T> &tb, const T *x, const T *xe, T *y, T *ye,
                         const double *ebar, bool use_ebar, T sign, int nrhs, const Flags *flags, int parity,
-                        double *vstress, hipStream_t s, bool stress, T *cutbuf, double *partial);
+                        double *vstress, hipStream_t s, bool stress, T *cutbuf, double *partial, bool allow_vm);
+
+// Cached voxel matrices (0; -2 allocation failed; -3 device error) and their release.
+int build_voxel_matrices(xfft_problem *p, bool fp32, bool fp64);
+void free_voxel_matrices(xfft_problem *p);
 
 // Allocation-free entry point: looks up this device's static scratch area
 // (once per device; call with the device current).  0 or XFFT_EDEVICE.

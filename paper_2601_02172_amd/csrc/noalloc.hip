@@ -88,7 +88,7 @@ extern "C" int xfft_apply_operator_noalloc(xfft_problem *p, const double *x_dev,
     // its corner-force rows before they are read, so nothing needs clearing
     launch_operator_ws<double>(p, p->t64, x_dev, x_dev + 3 * g.N, y_dev, y_dev + 3 * g.N, macro_strain_dev,
                                macro_strain_dev != nullptr, 1.0, 1, nullptr, 0, nullptr, s, avg_stress_dev != nullptr,
-                               cutbuf, partial);
+                               cutbuf, partial, false);
     const SlotLayout &L = p->slots;
     if (avg_stress_dev)
         k_avg_stress<<<1, 256, 0, s>>>(partial, L.fe0, L.fe_n, L.cut0, L.cut_n + L.enr_n, (double)g.N,

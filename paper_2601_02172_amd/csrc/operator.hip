@@ -631,12 +631,209 @@ __device__ __forceinline__ void enriched_block(const OpArgs<T> &A, int r, int bl
     }
 }
 
+// ---------------------------------------------------------------- cached voxel matrices
+// Column k of the matrix of irregular voxel q: the voxel's forces for the unit
+// input dof k (k < 24: FE component k % 3 of corner k / 3; k >= 24: enriched
+// dof (k - 24) of the corner, entering scaled by D0^-1/2), by the moment form
+// above in FP64; the outputs are the FE corner forces and the scaled enriched
+// corner forces, as the irregular-voxel kernel writes them.  Column k supplies
+// the rows i <= k of the packed upper triangle and the stress integral.
+__global__ __launch_bounds__(128) void k_vm_build(OpArgs<double> A, double *K64, float *K32) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t q = t / 48;
+    const int k = (int)(t - q * 48);
+    if (q >= A.nirr) return;
+    const uint32_t q32 = (uint32_t)q;
+    double Lc[8], U[8][3], Q[8][3], sc[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        Lc[c] = elem(A.irr_L + c * A.nirr, q32);
+        const int jc = elem(A.irr_j + c * A.nirr, q32);
+        sc[c] = jc >= 0 ? A.d0is[jc] : 0.0;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            U[c][d] = (k < 24 && 3 * c + d == k) ? 1.0 : 0.0;
+            Q[c][d] = (k >= 24 && 3 * c + d == k - 24) ? sc[c] : 0.0;
+        }
+    }
+    const Sym<double> eb = sym_zero<double>();
+    double F[8][3], Fe[8][3];
+#pragma unroll
+    for (int c = 0; c < 8; ++c)
+#pragma unroll
+        for (int d = 0; d < 3; ++d) F[c][d] = Fe[c][d] = acc_zero<double>();
+    Sym<double> S = sym_acc_zero<double>();
+    irregular_tet<0, double, false>(Lc, A.irr_M, A.nirr, q32, U, Q, A.irr_lab, A.lame, eb, F, Fe, S);
+    irregular_tet<1, double, false>(Lc, A.irr_M, A.nirr, q32, U, Q, A.irr_lab, A.lame, eb, F, Fe, S);
+    irregular_tet<2, double, false>(Lc, A.irr_M, A.nirr, q32, U, Q, A.irr_lab, A.lame, eb, F, Fe, S);
+    irregular_tet<3, double, false>(Lc, A.irr_M, A.nirr, q32, U, Q, A.irr_lab, A.lame, eb, F, Fe, S);
+    irregular_tet<4, double, false>(Lc, A.irr_M, A.nirr, q32, U, Q, A.irr_lab, A.lame, eb, F, Fe, S);
+    irregular_tet<5, double, false>(Lc, A.irr_M, A.nirr, q32, U, Q, A.irr_lab, A.lame, eb, F, Fe, S);
+    double *k64 = K64 + q * VM_STRIDE;
+    float *k32 = K32 ? K32 + q * VM_STRIDE : nullptr;
+#pragma unroll
+    for (int i = 0; i < 48; ++i) {
+        if (i <= k) {
+            const int c = (i < 24 ? i : i - 24) / 3, d = (i < 24 ? i : i - 24) % 3;
+            const double v = i < 24 ? F[c][d] : sc[c] * Fe[c][d];
+            k64[vm_row(i) + k] = v;
+            if (k32) k32[vm_row(i) + k] = (float)v;
+        }
+    }
+    const double st[6] = {S.xx, S.yy, S.zz, S.yz, S.xz, S.xy};
+#pragma unroll
+    for (int m = 0; m < 6; ++m) {
+        k64[VM_KP + 48 * m + k] = st[m];
+        if (k32) k32[VM_KP + 48 * m + k] = (float)st[m];
+    }
+    if (k < VM_KP - VM_K) {
+        k64[VM_K + k] = 0.0;
+        if (k32) k32[VM_K + k] = 0.0f;
+    }
+}
+
+template <typename T> struct VmArgs {
+    const T *x, *xe;          // inputs of load 0; loads 3 N / 3 nX apart
+    T *cutbuf;                // corner-force buffer of load 0
+    const T *K;               // [nirr][VM_STRIDE]
+    const int32_t *irr, *irr_j;
+    const Flags *flags;
+    int parity;
+    double *partial;
+    int nslots, slot0;
+    int n0, n1, n2;
+    int64_t N, nX, nirr;
+    int nrhs;
+};
+
+// One wave per irregular voxel (four voxels per wave in turn, 16 per
+// workgroup), every active load of the launch at once: the voxel's matrix is
+// read once for all loads.  Lane i < 48 owns row i (output dof i), lanes
+// 48..53 the stress rows; the packed matrix and the 48 inputs of every load are
+// staged in LDS.  Outputs go to the corner-force buffer exactly as the
+// moment-form kernel writes them.
+template <typename T, int NR, bool ST>
+__global__ __launch_bounds__(256) void k_irregular_vm(VmArgs<T> A) {
+    constexpr int KN = ST ? VM_STRIDE : VM_KP;
+    using V = typename std::conditional<sizeof(T) == 4, float4, double2>::type;
+    constexpr int PER_V = 16 / sizeof(T);
+    __shared__ V Ks4[4][KN / PER_V];
+    __shared__ T Xs[4][48][8];
+    __shared__ double red[4][VM_MAXR][6];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t blk = xcd_remap(blockIdx.x, gridDim.x);
+    const T *Ks = reinterpret_cast<const T *>(Ks4[wave]);
+    bool act[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) act[r] = r < A.nrhs && (A.flags == nullptr || A.flags[r].active[A.parity] != 0);
+    double sacc[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) sacc[r] = 0.0;
+    const int i = lane < 48 ? lane : 47;
+    const int Ri = vm_row(i);
+    const int m = lane - 48;                       // stress row of lanes 48..53
+    for (int v = 0; v < VM_VPW; ++v) {
+        const int64_t q = blk * VM_VPB + wave * VM_VPW + v;
+        const bool valid = q < A.nirr;             // uniform per wave
+        __syncthreads();                           // the previous voxel's LDS reads are done
+        if (valid) {
+            const V *Kq = reinterpret_cast<const V *>(A.K + q * VM_STRIDE);
+            for (int e = lane; e < KN / PER_V; e += 64) Ks4[wave][e] = Kq[e];
+            if (lane < 48) {
+                const int32_t vox = A.irr[q];
+                const int vi = vox % A.n0, vj = (vox / A.n0) % A.n1, vk = vox / (A.n0 * A.n1);
+                const int kk = lane < 24 ? lane : lane - 24;
+                const int c = kk / 3, d = kk - 3 * c;
+                int64_t src;
+                const T *base;
+                int64_t stride;
+                if (lane < 24) {
+                    src = wrapi(vi + (c & 1), A.n0) +
+                          (int64_t)A.n0 * (wrapi(vj + ((c >> 1) & 1), A.n1) + (int64_t)A.n1 * wrapi(vk + (c >> 2), A.n2)) +
+                          (int64_t)d * A.N;
+                    base = A.x;
+                    stride = 3 * A.N;
+                } else {
+                    const int jc = A.irr_j[c * A.nirr + q];
+                    src = jc >= 0 ? (int64_t)d * A.nX + jc : -1;
+                    base = A.xe;
+                    stride = 3 * A.nX;
+                }
+#pragma unroll
+                for (int r = 0; r < NR; ++r) Xs[wave][lane][r] = (act[r] && src >= 0) ? base[r * stride + src] : (T)0;
+            }
+        }
+        __syncthreads();
+        if (valid) {
+            if (lane < 48) {
+                T y[NR];
+#pragma unroll
+                for (int r = 0; r < NR; ++r) y[r] = acc_zero<T>();
+                // eight columns per step keep the loads in flight without
+                // holding the whole matrix row in registers
+#pragma unroll 1
+                for (int j0 = 0; j0 < 48; j0 += 8) {
+#pragma unroll
+                    for (int jj = 0; jj < 8; ++jj) {
+                        const int j = j0 + jj;
+                        const T kv = (j < i) ? Ks[vm_row(j) + i] : Ks[Ri + j];
+#pragma unroll
+                        for (int r = 0; r < NR; ++r) y[r] += kv * Xs[wave][j][r];
+                    }
+                }
+                const int kk = lane < 24 ? lane : lane - 24;
+                const int64_t half = cut_rows(A.nirr) * 24;
+#pragma unroll
+                for (int r = 0; r < NR; ++r) {
+                    if (act[r]) {
+                        T *cb = A.cutbuf + (int64_t)r * cut_rows(A.nirr) * 48 + (lane < 24 ? 0 : half);
+                        elem(cb, cut_index((uint32_t)q, kk)) = y[r];
+                    }
+                }
+            } else if (ST && m < 6) {
+                T sv[NR];
+#pragma unroll
+                for (int r = 0; r < NR; ++r) sv[r] = acc_zero<T>();
+#pragma unroll 1
+                for (int j0 = 0; j0 < 48; j0 += 8) {
+#pragma unroll
+                    for (int jj = 0; jj < 8; ++jj) {
+                        const T kv = Ks[VM_KP + 48 * m + j0 + jj];
+#pragma unroll
+                        for (int r = 0; r < NR; ++r) sv[r] += kv * Xs[wave][j0 + jj][r];
+                    }
+                }
+#pragma unroll
+                for (int r = 0; r < NR; ++r) sacc[r] += (double)sv[r];
+            }
+        }
+    }
+    if (ST && lane >= 48 && m < 6) {
+#pragma unroll
+        for (int r = 0; r < NR; ++r) red[wave][r][m] = sacc[r];
+    }
+    __syncthreads();
+    if (threadIdx.x < NR && threadIdx.x < A.nrhs) {
+        const int r = threadIdx.x;
+        double *P = A.partial + ((int64_t)r * A.nslots + A.slot0 + blk) * NPART;
+        P[0] = 0.0;
+#pragma unroll
+        for (int mm = 0; mm < 6; ++mm) P[1 + mm] = ST ? (red[0][r][mm] + red[1][r][mm]) + (red[2][r][mm] + red[3][r][mm]) : 0.0;
+    }
+}
+
+template <typename T, int NR>
+void launch_vm(const VmArgs<T> &A, unsigned grid, bool stress, hipStream_t s) {
+    if (stress) k_irregular_vm<T, NR, true><<<grid, 256, 0, s>>>(A);
+    else k_irregular_vm<T, NR, false><<<grid, 256, 0, s>>>(A);
+}
+
 }  // namespace
 
 template <typename T>
 void launch_operator_ws(xfft_problem *p, const Tables<T> &tb, const T *x, const T *xe, T *y, T *ye,
                         const double *ebar, bool use_ebar, T sign, int nrhs, const Flags *flags, int parity,
-                        double *vstress, hipStream_t s, bool stress, T *cutbuf, double *partial) {
+                        double *vstress, hipStream_t s, bool stress, T *cutbuf, double *partial, bool allow_vm) {
     const Geometry &g = p->g;
     const SlotLayout &L = p->slots;
     OpArgs<T> A;
@@ -654,7 +851,25 @@ void launch_operator_ws(xfft_problem *p, const Tables<T> &tb, const T *x, const 
     A.nrhs = nrhs;
     A.enr_slot0 = L.enr0;
     const bool hx = x != nullptr;
-    if (g.nirr > 0) {
+    // cached voxel matrices: operator applications without macro strain and
+    // voxel stresses (the CG iterations), up to VM_MAXR loads per launch
+    const T *vmK = sizeof(T) == 8 ? reinterpret_cast<const T *>(p->vm64) : reinterpret_cast<const T *>(p->vm32);
+    const bool vm = allow_vm && g.nirr > 0 && hx && !use_ebar && !vstress && nrhs <= VM_MAXR && vmK &&
+                    p->vm_valid && p->vm_on[sizeof(T) == 8 ? 1 : 0];
+    p->last_op_vm = vm;
+    if (vm) {
+        VmArgs<T> V;
+        V.x = x; V.xe = xe; V.cutbuf = cutbuf; V.K = vmK; V.irr = p->irr; V.irr_j = p->irr_j;
+        V.flags = flags; V.parity = parity; V.partial = partial; V.nslots = p->nslots; V.slot0 = L.vm0;
+        V.n0 = g.n0; V.n1 = g.n1; V.n2 = g.n2; V.N = g.N; V.nX = g.nX; V.nirr = g.nirr; V.nrhs = nrhs;
+        const unsigned grid = (unsigned)L.vm_n;
+        xfft_prof_mark(p, -1, s);
+        if (nrhs == 1) launch_vm<T, 1>(V, grid, stress, s);
+        else if (nrhs == 2) launch_vm<T, 2>(V, grid, stress, s);
+        else if (nrhs == 3) launch_vm<T, 3>(V, grid, stress, s);
+        else launch_vm<T, 6>(V, grid, stress, s);
+        xfft_prof_mark(p, K_IRREGULAR + (sizeof(T) == 8 ? K_COUNT : 0), s);
+    } else if (g.nirr > 0) {
         A.slot0 = L.cut0;
         dim3 grid((unsigned)L.cut_n * nrhs, 1);
         xfft_prof_mark(p, -1, s);
@@ -684,12 +899,49 @@ void launch_operator(xfft_problem *p, Work<T> &w, const Tables<T> &tb, const T *
                      bool use_ebar, T sign, int nrhs, const Flags *flags, int parity, double *vstress,
                      hipStream_t s, bool stress) {
     launch_operator_ws<T>(p, tb, x, xe, y, ye, p->ebar, use_ebar, sign, nrhs, flags, parity, vstress, s, stress,
-                          w.cutbuf, p->partial);
+                          w.cutbuf, p->partial, true);
+}
+
+// Cached voxel matrices of the current moduli for the requested precisions
+// (FP64 built by the moment form, FP32 rounded once from it).  0, or -2 when
+// the allocation fails (nothing is kept then), -3 on a launch error.
+int build_voxel_matrices(xfft_problem *p, bool fp32, bool fp64) {
+    const Geometry &g = p->g;
+    if (g.nirr == 0) return 0;
+    const size_t n = (size_t)g.nirr * VM_STRIDE;
+    if (fp64 && !p->vm64 && hipMalloc(&p->vm64, n * sizeof(double)) != hipSuccess) { p->vm64 = nullptr; return -2; }
+    if (fp32 && !p->vm32 && hipMalloc(&p->vm32, n * sizeof(float)) != hipSuccess) { p->vm32 = nullptr; return -2; }
+    // the FP32 table is rounded from the FP64 one: build FP64 in a temporary when only FP32 is kept
+    double *k64 = p->vm64;
+    bool tmp = false;
+    if (!k64) {
+        if (hipMalloc(&k64, n * sizeof(double)) != hipSuccess) return -2;
+        tmp = true;
+    }
+    OpArgs<double> A{};
+    A.irr_j = p->irr_j; A.irr_lab = p->irr_lab; A.irr_L = p->t64.irr_L; A.irr_M = p->t64.irr_M;
+    A.d0is = p->t64.d0is; A.lame = p->t64.lame; A.nirr = g.nirr;
+    const int64_t nt = g.nirr * 48;
+    k_vm_build<<<(unsigned)((nt + 127) / 128), 128, 0, p->stream>>>(A, k64, p->vm32);
+    const bool ok = hipGetLastError() == hipSuccess && hipStreamSynchronize(p->stream) == hipSuccess;
+    if (tmp) (void)hipFree(k64);
+    if (!ok) return -3;
+    p->vm_valid = true;
+    return 0;
+}
+
+void free_voxel_matrices(xfft_problem *p) {
+    if (p->vm64) (void)hipFree(p->vm64);
+    if (p->vm32) (void)hipFree(p->vm32);
+    p->vm64 = nullptr;
+    p->vm32 = nullptr;
+    p->vm_valid = false;
+    p->vm_on[0] = p->vm_on[1] = false;
 }
 
 template void launch_operator_ws<double>(xfft_problem *, const Tables<double> &, const double *, const double *,
                                          double *, double *, const double *, bool, double, int, const Flags *, int,
-                                         double *, hipStream_t, bool, double *, double *);
+                                         double *, hipStream_t, bool, double *, double *, bool);
 template void launch_operator<double>(xfft_problem *, Work<double> &, const Tables<double> &, const double *,
                                       const double *, double *, double *, bool, double, int, const Flags *, int,
                                       double *, hipStream_t, bool);
@@ -720,6 +972,7 @@ SlotLayout slot_layout(const Geometry &g) {
     set_depth(L, g, kz);
     L.cut0 = at; L.cut_n = (int)((g.nirr + 127) / 128); at += L.cut_n;
     L.enr0 = at; L.enr_n = (int)((g.nX + 255) / 256); at += L.enr_n;
+    L.vm0 = at; L.vm_n = (int)((g.nirr + VM_VPB - 1) / VM_VPB); at += L.vm_n;
     L.grn0 = at; L.grn_n = 0; // filled by the FFT planner
     L.total = at;
     return L;

@@ -43,6 +43,7 @@ class Options(ctypes.Structure):
         ("stream", ctypes.c_void_p),
         ("scheme", ctypes.c_int32),
         ("discretization", ctypes.c_int32),
+        ("voxel_matrices", ctypes.c_int32),
     ]
 
 
@@ -57,6 +58,7 @@ class Stats(ctypes.Structure):
         ("n_irregular_voxels", ctypes.c_int64),
         ("n_cut_elements", ctypes.c_int64),
         ("n_multilabel", ctypes.c_int64),
+        ("voxel_matrices", ctypes.c_int32),
     ]
 
 
@@ -155,7 +157,8 @@ class Problem:
 
     def __init__(self, n, length, levelset, phase, lame, *, rtol=1e-10, maxit=20000, precision="fp64",
                  snap_eps=1e-6, d0_scale=1.0, inner_rtol=1e-6, batch=True, device=0, check_every=8,
-                 use_graph=True, autotune=True, stream=None, scheme="lcg", discretization="xfem"):
+                 use_graph=True, autotune=True, stream=None, scheme="lcg", discretization="xfem",
+                 voxel_matrices="auto"):
         lib = _lib()
         self._h = None
         n = np.ascontiguousarray(n, dtype=np.int32)
@@ -176,6 +179,7 @@ class Problem:
         o.stream = stream
         o.scheme = _SCHEME[scheme]
         o.discretization = {"xfem": 0, "p1": 1}[discretization]
+        o.voxel_matrices = {"auto": -1, "never": 0, "always": 1}[voxel_matrices]
         h = ctypes.c_void_p()
         _check(lib.xfft_setup(_ip(n), _dp(length), _dp(L), _ip(ph), self.nphase, _dp(lame), ctypes.byref(o),
                               ctypes.byref(h)), "xfft_setup")
@@ -225,7 +229,8 @@ class Problem:
         out.update(avg_stress=avg, iters=iters, outer_iters=outer, final_res=res, converged=(rc == XFFT_OK),
                    seconds_setup=st.seconds_setup, seconds_solve=st.seconds_solve,
                    n_enriched=st.n_enriched, n_irregular_voxels=st.n_irregular_voxels,
-                   n_cut_elements=st.n_cut_elements, n_multilabel=st.n_multilabel)
+                   n_cut_elements=st.n_cut_elements, n_multilabel=st.n_multilabel,
+                   voxel_matrices=bool(st.voxel_matrices))
         if disp:
             out["disp"] = d
         if stress:
