@@ -144,8 +144,8 @@ __host__ __device__ inline int64_t cut_rows(int64_t nirr) { return (nirr + 63) &
 constexpr int VM_K = 1176;        // packed upper triangle
 constexpr int VM_KP = 1184;       // start of the stress rows (padded to 16 values)
 constexpr int VM_STRIDE = 1472;   // values per voxel
-constexpr int VM_VPW = 4;         // voxels per wave of the cached-matrix kernel
-constexpr int VM_VPB = 4 * VM_VPW;// voxels per 256-thread workgroup
+constexpr int VM_VPB = 4;         // fewest voxels per (one-wave) workgroup of the cached-matrix kernel
+constexpr int VM_GRID = 4096;     // most workgroups of a launch (each walks a contiguous chunk of voxels)
 constexpr int VM_MAXR = 6;        // loads per launch of the cached-matrix kernel
 __host__ __device__ constexpr int vm_row(int a) { return 47 * a - a * (a - 1) / 2; }
 

@@ -13,6 +13,7 @@
 //               corner forces of its (at most eight) irregular voxels (extra
 //               workgroups at the end of the k_regular launch).
 #include "kernels.h"
+#include <algorithm>
 #include <type_traits>
 #include "element.h"
 
@@ -706,23 +707,72 @@ template <typename T> struct VmArgs {
     int nrhs;
 };
 
-// One wave per irregular voxel (four voxels per wave in turn, 16 per
-// workgroup), every active load of the launch at once: the voxel's matrix is
+// Index data of irregular voxel q for the cached-matrix kernel, loaded two
+// voxels ahead of use: its voxel (lanes < 24 and >= 48) or the enriched index
+// of the lane's corner (lanes 24..47).  The address is selected, not branched
+// on, so that no control-flow join waits for the load.
+template <typename T>
+__device__ __forceinline__ int vm_index(const VmArgs<T> &A, int64_t q, int lane, int c) {
+    const bool enr = lane >= 24 && lane < 48;
+    const uintptr_t a = (uintptr_t)(A.irr + q), b = (uintptr_t)(A.irr_j + (enr ? c : 0) * A.nirr + q);
+    return *reinterpret_cast<const int32_t *>(enr ? b : a);
+}
+
+// Loads of irregular voxel q: this lane's share of the packed matrix (kreg)
+// and its input dof of every load (xreg; lanes < 48; zero where the dof does
+// not exist or the load is inactive).  Every load is issued unconditionally
+// from a valid address (the last lanes repeat the final matrix vector; lanes
+// without an input read node 0 of load 0) and validity is applied when the
+// values are used, so the arrays stay in registers and nothing waits here.
+template <typename T, typename V, int NR, int NV, int NVL>
+__device__ __forceinline__ void vm_fetch(const VmArgs<T> &A, int64_t q, int idx, int lane, int c, int d,
+                                         const bool (&act)[NR], V (&kreg)[NVL], T (&xreg)[NR], bool (&xok)[NR]) {
+    const V *Kq = reinterpret_cast<const V *>(A.K + q * VM_STRIDE);
+#pragma unroll
+    for (int u = 0; u < NVL; ++u) kreg[u] = Kq[min(lane + 64 * u, NV - 1)];
+    const bool fe = lane < 24, en = lane >= 24 && lane < 48 && idx >= 0;
+    const int vox = fe ? idx : 0;
+    const int vi = vox % A.n0, vj = (vox / A.n0) % A.n1, vk = vox / (A.n0 * A.n1);
+    const int cc = fe ? c : 0;
+    const int64_t node = wrapi(vi + (cc & 1), A.n0) +
+                         (int64_t)A.n0 * (wrapi(vj + ((cc >> 1) & 1), A.n1) + (int64_t)A.n1 * wrapi(vk + (cc >> 2), A.n2));
+    const uintptr_t pf = (uintptr_t)(A.x + (fe ? (int64_t)d * A.N + node : 0));
+    const uintptr_t pe = (uintptr_t)(A.xe + (en ? (int64_t)d * A.nX + idx : 0));
+    const T *src = reinterpret_cast<const T *>(en ? pe : pf);
+    const int64_t stride = en ? 3 * A.nX : 3 * A.N;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        xok[r] = act[r] && (fe || en);
+        xreg[r] = src[(xok[r] ? r : 0) * stride];
+    }
+}
+
+// 16-byte native vectors (HIP's float4 / double2 are unions, which keep arrays of
+// them in scratch memory)
+typedef float vf4 __attribute__((ext_vector_type(4)));
+typedef double vd2 __attribute__((ext_vector_type(2)));
+
+// One wave per workgroup, walking a contiguous chunk of irregular voxels; every
+// active load of the launch (up to VM_MAXR) at once, so each voxel's matrix is
 // read once for all loads.  Lane i < 48 owns row i (output dof i), lanes
-// 48..53 the stress rows; the packed matrix and the 48 inputs of every load are
-// staged in LDS.  Outputs go to the corner-force buffer exactly as the
-// moment-form kernel writes them.
+// 48..53 the stress rows (with the stress integral).  The matrix and the 48
+// inputs of each load are staged in LDS; those of the next voxel are loaded
+// into registers while the current one is computed.  Outputs go to the
+// corner-force buffer exactly as the moment-form kernel writes them.
 template <typename T, int NR, bool ST>
-__global__ __launch_bounds__(256) void k_irregular_vm(VmArgs<T> A) {
+__global__ __launch_bounds__(64) void k_irregular_vm(VmArgs<T> A) {
     constexpr int KN = ST ? VM_STRIDE : VM_KP;
-    using V = typename std::conditional<sizeof(T) == 4, float4, double2>::type;
+    using V = typename std::conditional<sizeof(T) == 4, vf4, vd2>::type;
     constexpr int PER_V = 16 / sizeof(T);
-    __shared__ V Ks4[4][KN / PER_V];
-    __shared__ T Xs[4][48][8];
-    __shared__ double red[4][VM_MAXR][6];
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    constexpr int NV = KN / PER_V, NVL = (NV + 63) / 64;     // vectors per voxel, per lane
+    __shared__ V Ks4[NV];
+    __shared__ V Xs4[48][8 / PER_V];          // the inputs of dof j, loads in order (padded to 8)
+    const int lane = threadIdx.x;
     const int64_t blk = xcd_remap(blockIdx.x, gridDim.x);
-    const T *Ks = reinterpret_cast<const T *>(Ks4[wave]);
+    const int64_t chunk = (A.nirr + gridDim.x - 1) / gridDim.x;
+    const int64_t q0 = blk * chunk, q1 = min(q0 + chunk, A.nirr);
+    const T *Ks = reinterpret_cast<const T *>(Ks4);
+    T *Xs = reinterpret_cast<T *>(Xs4);
     bool act[NR];
 #pragma unroll
     for (int r = 0; r < NR; ++r) act[r] = r < A.nrhs && (A.flags == nullptr || A.flags[r].active[A.parity] != 0);
@@ -731,101 +781,113 @@ __global__ __launch_bounds__(256) void k_irregular_vm(VmArgs<T> A) {
     for (int r = 0; r < NR; ++r) sacc[r] = 0.0;
     const int i = lane < 48 ? lane : 47;
     const int Ri = vm_row(i);
-    const int m = lane - 48;                       // stress row of lanes 48..53
-    for (int v = 0; v < VM_VPW; ++v) {
-        const int64_t q = blk * VM_VPB + wave * VM_VPW + v;
-        const bool valid = q < A.nirr;             // uniform per wave
-        __syncthreads();                           // the previous voxel's LDS reads are done
-        if (valid) {
-            const V *Kq = reinterpret_cast<const V *>(A.K + q * VM_STRIDE);
-            for (int e = lane; e < KN / PER_V; e += 64) Ks4[wave][e] = Kq[e];
-            if (lane < 48) {
-                const int32_t vox = A.irr[q];
-                const int vi = vox % A.n0, vj = (vox / A.n0) % A.n1, vk = vox / (A.n0 * A.n1);
-                const int kk = lane < 24 ? lane : lane - 24;
-                const int c = kk / 3, d = kk - 3 * c;
-                int64_t src;
-                const T *base;
-                int64_t stride;
-                if (lane < 24) {
-                    src = wrapi(vi + (c & 1), A.n0) +
-                          (int64_t)A.n0 * (wrapi(vj + ((c >> 1) & 1), A.n1) + (int64_t)A.n1 * wrapi(vk + (c >> 2), A.n2)) +
-                          (int64_t)d * A.N;
-                    base = A.x;
-                    stride = 3 * A.N;
-                } else {
-                    const int jc = A.irr_j[c * A.nirr + q];
-                    src = jc >= 0 ? (int64_t)d * A.nX + jc : -1;
-                    base = A.xe;
-                    stride = 3 * A.nX;
-                }
+    const int m = lane - 48;                        // stress row of lanes 48..53
+    const int kk = lane < 24 ? lane : lane - 24;    // corner-major dof of the lane's input and output
+    const int c = kk / 3, d = kk - 3 * c;
+    V kreg[NVL];
+    T xreg[NR];
+    bool xok[NR];
+    int idx_next = 0;
+    if (q0 < q1) {
+        vm_fetch<T, V, NR, NV, NVL>(A, q0, vm_index(A, q0, lane, c), lane, c, d, act, kreg, xreg, xok);
+        if (q0 + 1 < q1) idx_next = vm_index(A, q0 + 1, lane, c);
+    }
+    // The workgroup is one wave and the LDS accesses of a wave complete in
+    // order, so the hand-over through LDS needs only a compiler-level wave
+    // barrier; a workgroup barrier would also wait for the prefetch loads.
+    // Stores and loads share one in-order counter: a voxel's outputs are
+    // stored one step later, before the next prefetch is issued, so that
+    // waiting for the prefetch never waits for stores issued just before it.
+    T ylast[NR];
+    int64_t qlast = -1;
+    const int64_t half = cut_rows(A.nirr) * 24;
+    for (int64_t q = q0; q < q1; ++q) {
+        __builtin_amdgcn_wave_barrier();            // the previous voxel's LDS reads come first
 #pragma unroll
-                for (int r = 0; r < NR; ++r) Xs[wave][lane][r] = (act[r] && src >= 0) ? base[r * stride + src] : (T)0;
+        for (int u = 0; u < NVL; ++u)
+            if (lane + 64 * u < NV) Ks4[lane + 64 * u] = kreg[u];
+        if (lane < 48) {
+#pragma unroll
+            for (int r = 0; r < NR; ++r) Xs[8 * lane + r] = xok[r] ? xreg[r] : (T)0;
+        }
+        __builtin_amdgcn_wave_barrier();
+        if (qlast >= 0 && lane < 48) {
+#pragma unroll
+            for (int r = 0; r < NR; ++r) {
+                if (act[r]) {
+                    T *cb = A.cutbuf + (int64_t)r * cut_rows(A.nirr) * 48 + (lane < 24 ? 0 : half);
+                    elem(cb, cut_index((uint32_t)qlast, kk)) = ylast[r];
+                }
             }
         }
-        __syncthreads();
-        if (valid) {
+        // the next voxel's loads (its index data arrived during this voxel's
+        // predecessor) and the index data of the one after stay in flight
+        // while this voxel is computed
+        if (q + 1 < q1) {
+            vm_fetch<T, V, NR, NV, NVL>(A, q + 1, idx_next, lane, c, d, act, kreg, xreg, xok);
+            if (q + 2 < q1) idx_next = vm_index(A, q + 2, lane, c);
+        }
+        // lanes < 48: matrix row i; lanes 48..53 (with the stress integral):
+        // stress row m -- one loop, the lanes differ only in their address
+        if (lane < (ST ? 54 : 48)) {
+            T y[NR];
+#pragma unroll
+            for (int r = 0; r < NR; ++r) y[r] = acc_zero<T>();
+            // eight columns per step keep the loads in flight without holding
+            // the whole matrix row in registers
+#pragma unroll 1
+            for (int j0 = 0; j0 < 48; j0 += 8) {
+#pragma unroll
+                for (int jj = 0; jj < 8; ++jj) {
+                    const int j = j0 + jj;
+                    const int ka = lane < 48 ? ((j < i) ? vm_row(j) + i : Ri + j) : VM_KP + 48 * m + j;
+                    const T kv = Ks[ka];
+                    T xv[8];
+#pragma unroll
+                    for (int u = 0; u < (NR + PER_V - 1) / PER_V; ++u) {
+                        const V w = Xs4[j][u];
+#pragma unroll
+                        for (int e = 0; e < PER_V; ++e) xv[PER_V * u + e] = w[e];
+                    }
+#pragma unroll
+                    for (int r = 0; r < NR; ++r) y[r] += kv * xv[r];
+                }
+            }
             if (lane < 48) {
-                T y[NR];
 #pragma unroll
-                for (int r = 0; r < NR; ++r) y[r] = acc_zero<T>();
-                // eight columns per step keep the loads in flight without
-                // holding the whole matrix row in registers
-#pragma unroll 1
-                for (int j0 = 0; j0 < 48; j0 += 8) {
+                for (int r = 0; r < NR; ++r) ylast[r] = y[r];
+                qlast = q;
+            } else {
 #pragma unroll
-                    for (int jj = 0; jj < 8; ++jj) {
-                        const int j = j0 + jj;
-                        const T kv = (j < i) ? Ks[vm_row(j) + i] : Ks[Ri + j];
-#pragma unroll
-                        for (int r = 0; r < NR; ++r) y[r] += kv * Xs[wave][j][r];
-                    }
-                }
-                const int kk = lane < 24 ? lane : lane - 24;
-                const int64_t half = cut_rows(A.nirr) * 24;
-#pragma unroll
-                for (int r = 0; r < NR; ++r) {
-                    if (act[r]) {
-                        T *cb = A.cutbuf + (int64_t)r * cut_rows(A.nirr) * 48 + (lane < 24 ? 0 : half);
-                        elem(cb, cut_index((uint32_t)q, kk)) = y[r];
-                    }
-                }
-            } else if (ST && m < 6) {
-                T sv[NR];
-#pragma unroll
-                for (int r = 0; r < NR; ++r) sv[r] = acc_zero<T>();
-#pragma unroll 1
-                for (int j0 = 0; j0 < 48; j0 += 8) {
-#pragma unroll
-                    for (int jj = 0; jj < 8; ++jj) {
-                        const T kv = Ks[VM_KP + 48 * m + j0 + jj];
-#pragma unroll
-                        for (int r = 0; r < NR; ++r) sv[r] += kv * Xs[wave][j0 + jj][r];
-                    }
-                }
-#pragma unroll
-                for (int r = 0; r < NR; ++r) sacc[r] += (double)sv[r];
+                for (int r = 0; r < NR; ++r) sacc[r] += (double)y[r];
             }
         }
     }
-    if (ST && lane >= 48 && m < 6) {
+    if (qlast >= 0 && lane < 48) {
 #pragma unroll
-        for (int r = 0; r < NR; ++r) red[wave][r][m] = sacc[r];
+        for (int r = 0; r < NR; ++r) {
+            if (act[r]) {
+                T *cb = A.cutbuf + (int64_t)r * cut_rows(A.nirr) * 48 + (lane < 24 ? 0 : half);
+                elem(cb, cut_index((uint32_t)qlast, kk)) = ylast[r];
+            }
+        }
     }
-    __syncthreads();
-    if (threadIdx.x < NR && threadIdx.x < A.nrhs) {
-        const int r = threadIdx.x;
-        double *P = A.partial + ((int64_t)r * A.nslots + A.slot0 + blk) * NPART;
-        P[0] = 0.0;
+    // partial sums of the workgroup: no dot product; the stress integral by lanes 48..53
+    if (lane >= 48 && m < 7) {
 #pragma unroll
-        for (int mm = 0; mm < 6; ++mm) P[1 + mm] = ST ? (red[0][r][mm] + red[1][r][mm]) + (red[2][r][mm] + red[3][r][mm]) : 0.0;
+        for (int r = 0; r < NR; ++r) {
+            if (r < A.nrhs) {
+                double *P = A.partial + ((int64_t)r * A.nslots + A.slot0 + blk) * NPART;
+                P[m < 6 ? 1 + m : 0] = (ST && m < 6) ? sacc[r] : 0.0;
+            }
+        }
     }
 }
 
 template <typename T, int NR>
 void launch_vm(const VmArgs<T> &A, unsigned grid, bool stress, hipStream_t s) {
-    if (stress) k_irregular_vm<T, NR, true><<<grid, 256, 0, s>>>(A);
-    else k_irregular_vm<T, NR, false><<<grid, 256, 0, s>>>(A);
+    if (stress) k_irregular_vm<T, NR, true><<<grid, 64, 0, s>>>(A);
+    else k_irregular_vm<T, NR, false><<<grid, 64, 0, s>>>(A);
 }
 
 }  // namespace
@@ -972,7 +1034,7 @@ SlotLayout slot_layout(const Geometry &g) {
     set_depth(L, g, kz);
     L.cut0 = at; L.cut_n = (int)((g.nirr + 127) / 128); at += L.cut_n;
     L.enr0 = at; L.enr_n = (int)((g.nX + 255) / 256); at += L.enr_n;
-    L.vm0 = at; L.vm_n = (int)((g.nirr + VM_VPB - 1) / VM_VPB); at += L.vm_n;
+    L.vm0 = at; L.vm_n = (int)std::min<int64_t>((g.nirr + VM_VPB - 1) / VM_VPB, VM_GRID); at += L.vm_n;
     L.grn0 = at; L.grn_n = 0; // filled by the FFT planner
     L.total = at;
     return L;
