@@ -32,6 +32,10 @@ What it computes (voxel units, h = 1; Sec. 2 and Sec. 3 of the paper):
 * ``homogenize``  -- effective stiffness from the average stress, the energy
                      form and its closed-form derivative with respect to the
                      per-phase Lame parameters.
+* ``accuracy``    -- the accuracy measures of Sec. 4.1: relative error and the
+                     L^2 norm of local strain and stress fields by the
+                     discretisation's own quadrature (eqs. relError,
+                     L2NormGauss).
 """
 
 from .kuhn import CORNERS, kuhn_tets, bary_gradients

@@ -93,3 +93,67 @@ def isotropic_projection(C):
     K = np.trace(Jp @ C) / 3.0
     G = np.trace(Kp @ C) / 10.0
     return K, G
+
+
+def laminate_phase_strains(normal, fractions, lames, ebar):
+    """Uniform strain (Mandel) in each phase of a rank-one laminate (see laminate_phase_stresses)."""
+    out = []
+    for (lam, mu), sig in zip(lames, laminate_phase_stresses(normal, fractions, lames, ebar)):
+        S = np.linalg.inv(iso_stiffness(lam, mu))
+        out.append(S @ sig)
+    return out
+
+
+class CoatedSphereField:
+    """Exact field of a composite sphere (core radius ri, coating radius rc) in an
+    infinite matrix under the hydrostatic macro strain e I, all phases isotropic.
+
+    The displacement is radial, u = (A r + B / r^2) x / r in every phase (B = 0
+    in the core, and u = e x in the matrix when the sphere is neutral), so the
+    strain is A I + (B / r^3)(I - 3 n (x) n).  A and B follow from continuity of
+    u and of the radial traction 3 K A - 4 G B / r^3 at ri and continuity of u at
+    rc.  The remaining condition -- continuity of the radial traction at rc --
+    holds exactly when the matrix bulk modulus equals the composite-sphere bulk
+    modulus (the neutral inclusion); ``traction_jump`` reports its residual.
+    """
+
+    def __init__(self, K, G, ri, rc, e=1.0):
+        self.K = np.asarray(K, dtype=np.float64)       # (matrix, coating, core)
+        self.G = np.asarray(G, dtype=np.float64)
+        self.ri, self.rc, self.e = float(ri), float(rc), float(e)
+        Kc, Gc, Ki = self.K[1], self.G[1], self.K[2]
+        # unknowns (A_core, A_coat, B_coat)
+        M = np.array([[self.ri, -self.ri, -1.0 / self.ri ** 2],          # u continuous at ri
+                      [3.0 * Ki, -3.0 * Kc, 4.0 * Gc / self.ri ** 3],     # traction continuous at ri
+                      [0.0, self.rc, 1.0 / self.rc ** 2]])                # u = e rc at rc
+        self.Ai, self.Ac, self.Bc = np.linalg.solve(M, np.array([0.0, 0.0, self.e * self.rc]))
+
+    def traction_jump(self):
+        """Radial traction of the coating minus that of the matrix at rc."""
+        return 3.0 * self.K[1] * self.Ac - 4.0 * self.G[1] * self.Bc / self.rc ** 3 - 3.0 * self.K[0] * self.e
+
+    def phase_at(self, r):
+        return np.where(r >= self.rc, 0, np.where(r >= self.ri, 1, 2))
+
+    def strain(self, d):
+        """Total strain (Mandel, (m, 6)) and phase (m,) at offsets d (m, 3) from the centre."""
+        d = np.atleast_2d(d)
+        r = np.sqrt(np.sum(d * d, axis=1))
+        ph = self.phase_at(r)
+        A = np.where(ph == 0, self.e, np.where(ph == 1, self.Ac, self.Ai))
+        B = np.where(ph == 1, self.Bc, 0.0)
+        rs = np.where(r > 0, r, 1.0)
+        n = d / rs[:, None]
+        b = B / rs ** 3
+        E = A[:, None, None] * np.eye(3)[None] + b[:, None, None] * (np.eye(3)[None] - 3.0 * n[:, :, None] * n[:, None, :])
+        eps = np.stack([E[:, 0, 0], E[:, 1, 1], E[:, 2, 2], S2 * E[:, 1, 2], S2 * E[:, 0, 2], S2 * E[:, 0, 1]], axis=1)
+        return eps, ph
+
+    def displacement(self, d):
+        d = np.atleast_2d(d)
+        r = np.sqrt(np.sum(d * d, axis=1))
+        ph = self.phase_at(r)
+        A = np.where(ph == 0, self.e, np.where(ph == 1, self.Ac, self.Ai))
+        B = np.where(ph == 1, self.Bc, 0.0)
+        rs = np.where(r > 0, r, 1.0)
+        return (A + B / rs ** 3)[:, None] * d

@@ -12,6 +12,10 @@ ratio 0.25) under the macro strain I has the exact effective bulk modulus 1.
 * Schemes at N = 128, tol 1e-7 (the paper's solver study): every scheme reaches
   the tolerance, the basic scheme needs the most iterations and linear CG the
   fewest.
+* Oracle parity at N = 16: average stress, voxel stress field and linear-CG
+  iteration count against the CPU oracle (the relative L^2 errors of the local
+  fields against the textbook solution are pinned on the oracle side,
+  tests/test_oracle_accuracy.py).
 * Contrast sweep at N = 128 (the paper's contrast study): with the coating
   re-tuned to keep K_eff = 1 exact for core-to-coating bulk ratios 1e-4 ... 1e4,
   the error stays below 2e-3 and the iterations grow towards both a void-like
@@ -104,3 +108,29 @@ def test_hashin_contrast_sweep():
         assert err < 2e-3
     assert its[5.0] < its[1e2] < its[1e4]
     assert its[0.2] < its[1e-2] < its[1e-4]
+
+
+def test_hashin_fields_match_oracle_n16():
+    # the paper's own case at N = 16 against the oracle: <sigma>, the voxel
+    # stress field (eq. Sapp_q per voxel) at convergence, and the linear-CG
+    # iteration count to the paper's tolerance 1e-7 (within one)
+    from paper_2601_02172_amd import Problem
+    from oracle.xfem import Discretization
+    from oracle.homogenize import solve_loads
+    from oracle.system import System
+    N = 16
+    n, L, ph, lame = _hashin(N)
+    d = Discretization(n, (16.0,) * 3, L, ph, lame, keep_qp=False)
+    U, _ = solve_loads(d, EB, tol=1e-13)
+    s = System(d)
+    sig_or = s.average_stress(U[0], EB)
+    vs_or = s.voxel_stress(U[0], EB)
+    _, info7 = solve_loads(d, EB, tol=1e-7)
+    with Problem(n, [16.0] * 3, L, ph, lame, rtol=1e-12) as p:
+        r = p.solve(EB, stress=True)
+    with Problem(n, [16.0] * 3, L, ph, lame, rtol=1e-7, check_every=2) as p:
+        r7 = p.solve(EB)
+    assert r["converged"] and r7["converged"]
+    assert np.abs(r["avg_stress"][0] - sig_or).max() < 1e-10 * np.abs(sig_or).max()
+    assert np.abs(r["stress"][0] - vs_or).max() < 1e-9 * np.abs(vs_or).max()
+    assert abs(int(r7["iters"][0]) - int(info7[0]["iters"])) <= 1
