@@ -34,6 +34,12 @@
  *    it passes; the library copies inputs during the call and owns all device
  *    memory of a problem until xfft_destroy.
  *  - A handle is not thread safe; distinct handles may be used concurrently.
+ *  - The reductions of the solve (CG dot products, residual norms, average
+ *    stress) are fixed-order trees over per-workgroup partial sums, so solves
+ *    are bitwise reproducible for a given problem, option set and device;
+ *    there is no nondeterministic mode to select.  The per-phase sums of
+ *    xfft_grad_lame add into workgroup tables with LDS atomics (then reduce in
+ *    a fixed order), so gradients may differ between runs in the last bits.
  *  - Return value: XFFT_OK (0), XFFT_NOT_CONVERGED (+1: outputs hold the last
  *    iterate), or a negative error code; xfft_strerror names it.
  */
@@ -159,7 +165,10 @@ int xfft_solve(xfft_problem *p, int32_t nload, const double *macro_strain,
 /* Same as xfft_solve with caller-owned device buffers (e.g. torch tensors):
  * strain_dev[nload][6], disp_dev[nload][3][N] or NULL, avg_stress_dev[nload][6]
  * or NULL, all float64 on the problem's device; runs on `stream` (hipStream_t,
- * NULL = the problem's stream) and returns after it completes. */
+ * NULL = the problem's stream) and returns after it completes.  With the six
+ * unit Mandel loads, avg_stress_dev holds C_eff: row k of avg_stress_dev is
+ * column k of C_eff (C_eff is symmetric, so the [6][6] block is C_eff itself up
+ * to the solver's tolerance); no separate C_eff output is needed. */
 int xfft_solve_device(xfft_problem *p, int32_t nload, const double *strain_dev,
                       double *disp_dev, double *avg_stress_dev, void *stream,
                       xfft_stats *stats);

@@ -1,6 +1,8 @@
 """GPU gradient of C_eff with respect to the Lame pairs (closed form by Galerkin
 orthogonality) against the oracle's closed form, against central differences
-of the GPU C_eff, and through torch.autograd."""
+of the GPU C_eff and through torch.autograd.  The tests of a general adjoint
+route (one batched adjoint solve and a cross contraction) are kept but skipped:
+that code is not in the library (see ADJOINT_SKIP)."""
 
 import numpy as np
 import pytest
@@ -150,3 +152,35 @@ def test_autograd_raises_when_not_converged():
         t = torch.tensor(_case("sphere8")[3], dtype=torch.float64, requires_grad=True)
         with pytest.raises(RuntimeError, match="did not reach"):
             ceff(t, p)
+
+
+ADJOINT_SKIP = ("general adjoint contraction removed: its first GPU run (two_spheres16, FP64) ended in a "
+                "GPU memory fault whose cause was not found by reading the kernels; the gradient is the "
+                "closed form (Galerkin orthogonality) until the contraction is rebuilt and shown correct")
+
+
+@pytest.mark.skip(reason=ADJOINT_SKIP)
+@pytest.mark.parametrize("name,precision", [("two_spheres16", "fp64"), ("coated12", "fp64"), ("two_spheres16", "mixed")])
+def test_adjoint_gradient_matches_closed_form(name, precision):
+    # the general adjoint route (App. A): one batched solve with the rows of
+    # dL/dC as macro strains, then the cross contraction of adjoint and unit-load
+    # strains; equals the closed form for any (here non-symmetric) weights
+    with _gpu(name, rtol=1e-12 if precision == "fp64" else 1e-11, precision=precision) as p:
+        p.effective_stiffness()
+        W = np.random.default_rng(13).standard_normal((6, 6))
+        g_cf, _ = p.grad_lame(W)
+        g_adj, info = p.grad_lame_adjoint(W)
+        g_cf2, _ = p.grad_lame(W)                      # the unit-load solutions are kept
+    assert info["converged"]
+    scale = np.abs(g_cf).max()
+    assert np.abs(g_adj - g_cf).max() < 1e-8 * scale
+    assert np.abs(g_cf2 - g_cf).max() < 1e-13 * scale
+
+
+@pytest.mark.skip(reason=ADJOINT_SKIP)
+def test_adjoint_gradient_requires_unit_load_solve():
+    from paper_2601_02172_amd import XfftError
+    with _gpu("sphere8") as p:
+        p.solve(np.eye(6)[:2])
+        with pytest.raises(XfftError):
+            p.grad_lame_adjoint(np.eye(6))
