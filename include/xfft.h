@@ -112,6 +112,11 @@ typedef struct {
                                0 never; 1 always (also for xfft_apply_operator).  Costs 11.8 KB (FP64) / 5.9 KB
                                (FP32) of device memory per irregular voxel; falls back to the moment form when the
                                allocation fails.  Rebuilt after xfft_set_lame. */
+    int32_t warm_start;     /* 1: a solve of the six unit Mandel loads starts the CG of each load from that load's
+                               solution of the previous unit-load solve of this problem (same geometry, possibly
+                               other moduli after xfft_set_lame) instead of u = 0; other solves, and the first
+                               one, start from 0.  The converged result does not depend on the start; the stopping
+                               test of eq. stoppingCriterion is the same.  Default 0. */
 } xfft_options;
 
 typedef struct {

@@ -360,8 +360,11 @@ int final_outputs(xfft_problem *p, int nrhs, double *avg_host, double *vstress_d
 }
 
 // Solve nrhs loads whose macro strains are in ebar_host; solution left in w64.u/ue.
+// u0, ue0: device start iterates [nrhs][3][N], [nrhs][3][nX] (FP64, voxel
+// units), or null to start from u = 0.
 int solve_block(xfft_problem *p, int nrhs, const double *ebar_host, std::vector<int> &iters,
-                std::vector<int> &outer, std::vector<double> &res_rel, int *status) {
+                std::vector<int> &outer, std::vector<double> &res_rel, int *status,
+                const double *u0 = nullptr, const double *ue0 = nullptr) {
     int rc = alloc_work<double>(p, p->w64, nrhs);
     if (rc) return rc;
     if (p->precision == XFFT_MIXED) {
@@ -387,8 +390,14 @@ int solve_block(xfft_problem *p, int nrhs, const double *ebar_host, std::vector<
     hipStream_t s = p->stream;
     Work<double> &w = p->w64;
     const size_t nf = sizeof(double) * 3 * p->g.N * nrhs, ne = sizeof(double) * 3 * p->g.nX * nrhs;
-    HIP_OK(hipMemsetAsync(w.u, 0, nf, s));
-    if (ne) HIP_OK(hipMemsetAsync(w.ue, 0, ne, s));
+    const bool warm = u0 != nullptr;
+    if (warm) {
+        HIP_OK(hipMemcpyAsync(w.u, u0, nf, hipMemcpyDeviceToDevice, s));
+        if (ne) HIP_OK(hipMemcpyAsync(w.ue, ue0, ne, hipMemcpyDeviceToDevice, s));
+    } else {
+        HIP_OK(hipMemsetAsync(w.u, 0, nf, s));
+        if (ne) HIP_OK(hipMemsetAsync(w.ue, 0, ne, s));
+    }
     p->sigma_ready = false;
     iters.assign(nrhs, 0);
     outer.assign(nrhs, 0);
@@ -396,8 +405,9 @@ int solve_block(xfft_problem *p, int nrhs, const double *ebar_host, std::vector<
     std::vector<Flags> fl;
     *status = XFFT_OK;
     if (p->precision != XFFT_MIXED) {
-        // f = b = -r(0)
-        launch_operator<double>(p, w, p->t64, nullptr, nullptr, w.f, w.fe, true, -1.0, nrhs, nullptr, 0, nullptr, s);
+        // f = b - A u0 = -r(u0) (u0 = 0 unless warm started)
+        launch_operator<double>(p, w, p->t64, warm ? w.u : nullptr, w.ue, w.f, w.fe, true, -1.0, nrhs, nullptr, 0,
+                                nullptr, s);
         launch_scalars(p, SC_INIT_SIGMA, 0, nrhs, 0, nullptr, s, true);
         cg_start<double>(p, w, p->t64, nrhs, 0);
         cg_loop<double>(p, w, p->t64, nrhs, 0, &rc);
@@ -415,8 +425,8 @@ int solve_block(xfft_problem *p, int nrhs, const double *ebar_host, std::vector<
         bool all_done = false;
         for (int o = 0; o < max_outer && !all_done; ++o) {
             // r = b - A u in FP64 (also gives the exact <sigma(u)>)
-            launch_operator<double>(p, w, p->t64, o == 0 ? nullptr : w.u, w.ue, w.f, w.fe, true, -1.0, nrhs, nullptr,
-                                    0, nullptr, s);
+            launch_operator<double>(p, w, p->t64, (o == 0 && !warm) ? nullptr : w.u, w.ue, w.f, w.fe, true, -1.0,
+                                    nrhs, nullptr, 0, nullptr, s);
             launch_scalars(p, SC_INIT_SIGMA, 0, nrhs, 0, nullptr, s, true);
             launch_round_to_float(p, nrhs, s);
             cg_start<float>(p, w32, p->t32, nrhs, 0);     // outer criterion on the FP64 residual
@@ -494,13 +504,18 @@ int solve_impl(xfft_problem *p, int nload, const double *strain, double *disp, d
         }
     }
     p->sol_unit_basis = false;
+    // warm start: the stored unit-load solutions of an earlier solve
+    const bool warm = unit && p->warm_start && p->sol_stored;
+    p->sol_stored = false;
     double *vstress_dev = nullptr;
     for (int l0 = 0; l0 < nload; l0 += blk) {
         const int nr = (l0 + blk <= nload) ? blk : nload - l0;
         std::vector<int> it, outer;
         std::vector<double> res;
         int st = XFFT_OK;
-        int rc = solve_block(p, nr, strain + 6 * l0, it, outer, res, &st);
+        int rc = solve_block(p, nr, strain + 6 * l0, it, outer, res, &st,
+                             warm ? p->sol_u + (size_t)3 * N * l0 : nullptr,
+                             warm ? p->sol_ue + (size_t)3 * nX * l0 : nullptr);
         if (rc) return rc;
         if (st == XFFT_EBREAKDOWN || (st == XFFT_NOT_CONVERGED && status == XFFT_OK)) status = st;
         if (stress) {
@@ -547,6 +562,8 @@ int solve_impl(xfft_problem *p, int nload, const double *strain, double *disp, d
     }
     if (stress && !device_out && vstress_dev) (void)hipFree(vstress_dev);
     if (unit) p->sol_unit_basis = true;
+    // finite solutions to start a later warm-started solve from
+    if (unit) p->sol_stored = status == XFFT_OK || status == XFFT_NOT_CONVERGED;
     if (avg_stress) {
         if (device_out) HIP_OK(hipMemcpy(avg_stress, avg.data(), sizeof(double) * 6 * nload, hipMemcpyHostToDevice));
         else std::memcpy(avg_stress, avg.data(), sizeof(double) * 6 * nload);
@@ -696,6 +713,7 @@ void xfft_default_options(xfft_options *opt) {
     opt->scheme = XFFT_LCG;
     opt->discretization = XFFT_XFEM;
     opt->voxel_matrices = -1;
+    opt->warm_start = 0;
 }
 
 const char *xfft_strerror(int code) {
@@ -765,7 +783,7 @@ int xfft_setup(const int32_t n[3], const double len[3], const double *levelset, 
         (opt.precision != XFFT_FP64 && opt.precision != XFFT_MIXED) || opt.scheme < XFFT_LCG ||
         opt.scheme > XFFT_BASIC || (opt.scheme != XFFT_LCG && opt.precision != XFFT_FP64) ||
         (opt.discretization != XFFT_XFEM && opt.discretization != XFFT_P1) || opt.voxel_matrices < -1 ||
-        opt.voxel_matrices > 1)
+        opt.voxel_matrices > 1 || opt.warm_start < 0 || opt.warm_start > 1)
         return XFFT_EINVAL;
     const double t0 = now_s();
     int ndev = 0;
@@ -791,6 +809,7 @@ int xfft_setup(const int32_t n[3], const double len[3], const double *levelset, 
     p->scheme = opt.scheme;
     p->p1 = opt.discretization == XFFT_P1 ? 1 : 0;
     p->vm_mode = opt.voxel_matrices;
+    p->warm_start = opt.warm_start != 0;
     if (opt.stream) {
         p->stream = (hipStream_t)opt.stream;
     } else {
@@ -1198,6 +1217,10 @@ int xfft_batch_solve(xfft_problem *const *ps, int32_t nprob, double *c_eff, xfft
                                   p->stream));
         HIP_OK(hipStreamSynchronize(p->stream));
         p->sol_unit_basis = true;
+        bool finite = true;
+        for (int q = 0; q < nl; ++q)
+            if (f[q].breakdown) finite = false;
+        p->sol_stored = finite;
         if (stats) {
             xfft_stats &st = stats[i];
             for (int q = 0; q < nl; ++q) {

@@ -238,6 +238,10 @@ struct xfft_problem {
     double *sol_u = nullptr, *sol_ue = nullptr;
     int sol_nload = 0;
     bool sol_unit_basis = false;
+    // sol_u / sol_ue hold finite unit-load solutions of an earlier solve (any
+    // moduli): the start of a warm-started unit-load solve
+    bool sol_stored = false;
+    bool warm_start = false;
     double seconds_setup = 0.0, seconds_solve = 0.0;
     // captured CG iterations (replayed as one hipGraph launch)
     bool use_graph = true;

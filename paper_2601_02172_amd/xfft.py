@@ -44,6 +44,7 @@ class Options(ctypes.Structure):
         ("scheme", ctypes.c_int32),
         ("discretization", ctypes.c_int32),
         ("voxel_matrices", ctypes.c_int32),
+        ("warm_start", ctypes.c_int32),
     ]
 
 
@@ -158,7 +159,7 @@ class Problem:
     def __init__(self, n, length, levelset, phase, lame, *, rtol=1e-10, maxit=20000, precision="fp64",
                  snap_eps=1e-6, d0_scale=1.0, inner_rtol=1e-6, batch=True, device=0, check_every=8,
                  use_graph=True, autotune=True, stream=None, scheme="lcg", discretization="xfem",
-                 voxel_matrices="auto"):
+                 voxel_matrices="auto", warm_start=False):
         lib = _lib()
         self._h = None
         n = np.ascontiguousarray(n, dtype=np.int32)
@@ -180,6 +181,7 @@ class Problem:
         o.scheme = _SCHEME[scheme]
         o.discretization = {"xfem": 0, "p1": 1}[discretization]
         o.voxel_matrices = {"auto": -1, "never": 0, "always": 1}[voxel_matrices]
+        o.warm_start = int(bool(warm_start))
         h = ctypes.c_void_p()
         _check(lib.xfft_setup(_ip(n), _dp(length), _dp(L), _ip(ph), self.nphase, _dp(lame), ctypes.byref(o),
                               ctypes.byref(h)), "xfft_setup")

@@ -191,6 +191,8 @@ int main(void) {
         BAD_OPT(discretization, 2);
         BAD_OPT(voxel_matrices, 2);
         BAD_OPT(voxel_matrices, -2);
+        BAD_OPT(warm_start, 2);
+        BAD_OPT(warm_start, -1);
         xfft_default_options(&o);
         o.scheme = XFFT_NLCG;
         o.precision = XFFT_MIXED;
@@ -200,6 +202,9 @@ int main(void) {
         expect_valid(&c, &o, "Barzilai-Borwein FP64");
         o.discretization = XFFT_P1;
         expect_valid(&c, &o, "P1 discretisation");
+        xfft_default_options(&o);
+        o.warm_start = 1;
+        expect_valid(&c, &o, "warm start");
 #undef BAD_OPT
     }
 
