@@ -117,6 +117,13 @@ typedef struct {
                                other moduli after xfft_set_lame) instead of u = 0; other solves, and the first
                                one, start from 0.  The converged result does not depend on the start; the stopping
                                test of eq. stoppingCriterion is the same.  Default 0. */
+    int32_t fft_variant;    /* kernels of the Green operator (eq. GreenHermitian): -1 (default) timed at the first
+                               solve of a precision, the fastest kept (with autotune on; else 0); or fixed: bit 0
+                               set = separate x and y passes instead of the xy-plane kernels (grids with
+                               n0 = n1 in {16, 32, 48, 64, 96, 128}), bit 1 set = the alternative z-pass tile
+                               (twice the kx columns per workgroup at n2 = 256, half of them for the other
+                               compile-time lengths 16 ... 128).  A bit a grid has no choice for is ignored.
+                               Every variant computes the same transform. */
 } xfft_options;
 
 typedef struct {
@@ -130,6 +137,7 @@ typedef struct {
     int64_t n_cut_elements;
     int64_t n_multilabel;  /* cut elements whose vertices on one side carry different labels */
     int32_t voxel_matrices;/* 1 if the CG iterations of the last solve used the cached voxel matrices */
+    int32_t fft_variant;   /* FFT variant (bits as option fft_variant) of the last solve's CG iterations */
 } xfft_stats;
 
 /* Fill *opt with the defaults listed above. */

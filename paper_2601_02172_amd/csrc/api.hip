@@ -263,6 +263,58 @@ int autotune_depth(xfft_problem *p, Work<T> &w, const Tables<T> &tb, int nrhs) {
     return XFFT_OK;
 }
 
+// Choose the Green-operator kernels (xy-plane kernels or separate x and y
+// passes, z-pass tile) by timing a forward and inverse application of every
+// variant the grid has in the solve's launch configuration; results are cached
+// per (grid, precision, loads) for the process.
+template <typename T>
+int autotune_fft(xfft_problem *p, Work<T> &w, const Tables<T> &tb, int nrhs) {
+    const int pi = sizeof(T) == 8 ? 1 : 0;
+    if (p->fft_tuned[pi]) return XFFT_OK;
+    static std::map<std::array<int, 5>, int> cache;
+    const std::array<int, 5> key = {p->g.n0, p->g.n1, p->g.n2, (int)sizeof(T), nrhs};
+    const int have = fft_variants<T>(p->g);
+    int best = 0;
+    auto it = cache.find(key);
+    if (it != cache.end()) {
+        best = it->second;
+    } else if (have) {
+        hipStream_t s = p->stream;
+        // zero input: the timed transforms read defined values
+        HIP_OK(hipMemsetAsync(w.f, 0, sizeof(T) * 3 * p->g.N * nrhs, s));
+        if (p->g.nX) HIP_OK(hipMemsetAsync(w.fe, 0, sizeof(T) * 3 * p->g.nX * nrhs, s));
+        hipEvent_t e0, e1;
+        HIP_OK(hipEventCreate(&e0));
+        HIP_OK(hipEventCreate(&e1));
+        float best_ms = 1e30f;
+        for (int v = 0; v < 4; ++v) {
+            if ((v & ~have) != 0) continue;
+            p->fft_plane[pi] = (v & 1) ? 0 : 1;
+            p->fft_ztile[pi] = (v >> 1) & 1;
+            launch_green_forward<T>(p, w, tb, w.f, nullptr, nrhs, nullptr, 0, s, 0, nullptr);
+            launch_green_inverse<T>(p, w, tb, 2, nullptr, nrhs, nullptr, 0, s, 2);
+            (void)hipEventRecord(e0, s);
+            for (int rep = 0; rep < 5; ++rep) {
+                launch_green_forward<T>(p, w, tb, w.f, nullptr, nrhs, nullptr, 0, s, 0, nullptr);
+                launch_green_inverse<T>(p, w, tb, 2, nullptr, nrhs, nullptr, 0, s, 2);
+            }
+            (void)hipEventRecord(e1, s);
+            float ms = 0.0f;
+            if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) break;
+            if (ms < best_ms) { best_ms = ms; best = v; }
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        if (hipGetLastError() != hipSuccess) return XFFT_EDEVICE;
+        cache[key] = best;
+    }
+    p->fft_plane[pi] = (best & 1) ? 0 : 1;
+    p->fft_ztile[pi] = (best >> 1) & 1;
+    p->fft_tuned[pi] = true;
+    drop_graph(p);
+    return XFFT_OK;
+}
+
 // Cached voxel matrices for the CG iterations of precision T in the launch
 // configuration (nrhs, stress integral on or off): never, always, or -- the
 // default -- whichever of the moment form and the cached matrices applies the
@@ -380,6 +432,9 @@ int solve_block(xfft_problem *p, int nrhs, const double *ebar_host, std::vector<
         p->tuned = true;
         drop_graph(p);
     }
+    rc = (p->precision == XFFT_MIXED) ? autotune_fft<float>(p, p->w32, p->t32, nrhs)
+                                      : autotune_fft<double>(p, p->w64, p->t64, nrhs);
+    if (rc) return rc;
     // the CG iterations: FP32 without the stress integral inside the refinement,
     // FP64 with it (criterion 0 tracks <sigma>)
     rc = (p->precision == XFFT_MIXED) ? ensure_voxel_matrices<float>(p, p->w32, p->t32, nrhs, false)
@@ -581,6 +636,8 @@ int solve_impl(xfft_problem *p, int nload, const double *strain, double *disp, d
         stats->n_cut_elements = p->n_cut_elements;
         stats->n_multilabel = p->n_multilabel;
         stats->voxel_matrices = p->vm_on[p->precision == XFFT_MIXED ? 0 : 1] ? 1 : 0;
+        const int pi = p->precision == XFFT_MIXED ? 0 : 1;
+        stats->fft_variant = (p->fft_plane[pi] ? 0 : 1) | (p->fft_ztile[pi] ? 2 : 0);
     }
     return status;
 }
@@ -714,6 +771,7 @@ void xfft_default_options(xfft_options *opt) {
     opt->discretization = XFFT_XFEM;
     opt->voxel_matrices = -1;
     opt->warm_start = 0;
+    opt->fft_variant = -1;
 }
 
 const char *xfft_strerror(int code) {
@@ -783,7 +841,8 @@ int xfft_setup(const int32_t n[3], const double len[3], const double *levelset, 
         (opt.precision != XFFT_FP64 && opt.precision != XFFT_MIXED) || opt.scheme < XFFT_LCG ||
         opt.scheme > XFFT_BASIC || (opt.scheme != XFFT_LCG && opt.precision != XFFT_FP64) ||
         (opt.discretization != XFFT_XFEM && opt.discretization != XFFT_P1) || opt.voxel_matrices < -1 ||
-        opt.voxel_matrices > 1 || opt.warm_start < 0 || opt.warm_start > 1)
+        opt.voxel_matrices > 1 || opt.warm_start < 0 || opt.warm_start > 1 || opt.fft_variant < -1 ||
+        opt.fft_variant > 3)
         return XFFT_EINVAL;
     const double t0 = now_s();
     int ndev = 0;
@@ -810,6 +869,14 @@ int xfft_setup(const int32_t n[3], const double len[3], const double *levelset, 
     p->p1 = opt.discretization == XFFT_P1 ? 1 : 0;
     p->vm_mode = opt.voxel_matrices;
     p->warm_start = opt.warm_start != 0;
+    if (opt.fft_variant >= 0 || !p->autotune) {
+        const int v = opt.fft_variant > 0 ? opt.fft_variant : 0;
+        for (int q = 0; q < 2; ++q) {
+            p->fft_plane[q] = (v & 1) ? 0 : 1;
+            p->fft_ztile[q] = (v >> 1) & 1;
+            p->fft_tuned[q] = true;
+        }
+    }
     if (opt.stream) {
         p->stream = (hipStream_t)opt.stream;
     } else {

@@ -177,7 +177,7 @@ void launch_scalars(xfft_problem *p, int op, int crit, int nrhs, int parity, dou
         A.n1 = p->last_op_vm ? L.enr_n + L.vm_n : L.cut_n + L.enr_n;
     } else {
         A.s0 = L.grn0;
-        A.n = fp64 ? green_blocks<double>(p->g) : green_blocks<float>(p->g);
+        A.n = fp64 ? green_blocks<double>(p) : green_blocks<float>(p);
         A.s1 = L.eu0;
         A.n1 = L.eu_n;
     }

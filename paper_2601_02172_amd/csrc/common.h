@@ -251,6 +251,13 @@ struct xfft_problem {
     const void *graph_ptrs[3] = {nullptr, nullptr, nullptr};
     bool autotune = true;
     bool tuned = false;
+    // FFT variant per precision ([0] FP32, [1] FP64): xy-plane kernels (1) or
+    // separate x and y passes (0) where both exist, and the z-pass tile (0:
+    // default columns per workgroup, 1: the alternative); fixed by the option
+    // fft_variant or timed at the first solve of a precision
+    int fft_plane[2] = {1, 1};
+    int fft_ztile[2] = {0, 0};
+    bool fft_tuned[2] = {false, false};
     // cached voxel matrices: option (-1 autotuned, 0 never, 1 always), the
     // tables of each precision (built for the current moduli) and whether the
     // CG iterations of that precision use them

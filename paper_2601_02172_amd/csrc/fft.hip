@@ -20,6 +20,8 @@
 #include "enriched.h"
 #include "fft_lines.h"
 
+#include <algorithm>
+
 namespace xfft {
 
 FftPlan make_plan(int n) {
@@ -791,7 +793,10 @@ __global__ __launch_bounds__(1024) void k_fft_plane_inv(FftArgs A, const cpx<T> 
 // rows apart, so that the 16 columns x 2 rows of a half wave fall on 32
 // different banks in the staging and Green phases too.
 template <typename T, int N2, int TK>
-__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 8 : 1)))
+// FP32 tiles of up to 2048 staged values per component are held to 64
+// registers (eight waves per SIMD); larger tiles fit one workgroup per CU in
+// LDS, so they keep their registers
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && TK * N2 <= 2048 ? 8 : 1)))
 void k_fft_z_t(FftArgs A, const cpx<T> *tw, const T *h0, const T *h1,
                                                   const T *h2, cpx<T> *spec, int64_t sz, int64_t sy, int nrhs,
                                                   EnrUpd<T> E) {
@@ -969,9 +974,16 @@ template <typename T> static bool plane_path(const Geometry &g) {
     return g.n0 == g.n1 && plane_size(g.n0) &&
            (size_t)(g.n0 / 2 + 1) * lds_ls<true>(g.n0) * sizeof(cpx<T>) <= (size_t)160 * 1024;
 }
+// the xy-plane kernels run when the grid has them and the problem's variant selects them
+template <typename T> static bool use_plane(const xfft_problem *p) {
+    return plane_path<T>(p->g) && p->fft_plane[sizeof(T) == 8 ? 1 : 0] != 0;
+}
 // kx columns per z-pass workgroup: 3 x TK lines of n2 complex values in LDS
 // (about 50 KB, three workgroups per CU)
 template <typename T> static constexpr int tkz_t(int n2) { return (sizeof(T) == 8 ? 8 : 16) / (n2 >= 256 ? 2 : 1); }
+// the alternative tile: twice the columns at n2 = 256 (128-byte runs in FP32,
+// one or two workgroups per CU), half of them below (more workgroups per CU)
+template <typename T> static constexpr int tkz_alt(int n2) { return n2 >= 256 ? 2 * tkz_t<T>(n2) : tkz_t<T>(n2) / 2; }
 
 // The generic passes run every line of a workgroup through lds_fft, which
 // handles at most MAXB * threads butterflies per stage, and hold their lines
@@ -1005,16 +1017,30 @@ bool fft_sizes_ok(int n0, int n1, int n2) {
     return fft_fits<double>(g) && fft_fits<float>(g);
 }
 
-template <typename T> int green_blocks(const Geometry &g) {
-    const int tk = ztmpl_size(g.n2) ? tkz_t<T>(g.n2) : tk_z(g);
+template <typename T> static int green_blocks_tk(const Geometry &g, int ztile) {
+    const int tk = ztmpl_size(g.n2) ? (ztile ? tkz_alt<T>(g.n2) : tkz_t<T>(g.n2)) : tk_z(g);
     return g.n1 * ((g.nh + tk - 1) / tk);
 }
-template int green_blocks<double>(const Geometry &);
-template int green_blocks<float>(const Geometry &);
+template <typename T> int green_blocks(const xfft_problem *p) {
+    return green_blocks_tk<T>(p->g, p->fft_ztile[sizeof(T) == 8 ? 1 : 0]);
+}
+template int green_blocks<double>(const xfft_problem *);
+template int green_blocks<float>(const xfft_problem *);
 
+template <typename T> int fft_variants(const Geometry &g) {
+    return (plane_path<T>(g) ? 1 : 0) | (ztmpl_size(g.n2) ? 2 : 0);
+}
+template int fft_variants<double>(const Geometry &);
+template int fft_variants<float>(const Geometry &);
+
+// partial-sum slots for the z pass: the most workgroups any variant launches
 int green_slots(const Geometry &g) {
-    const int a = green_blocks<double>(g), b = green_blocks<float>(g);
-    return a > b ? a : b;
+    int m = 0;
+    for (int zt = 0; zt < 2; ++zt) {
+        m = std::max(m, green_blocks_tk<double>(g, zt));
+        m = std::max(m, green_blocks_tk<float>(g, zt));
+    }
+    return m;
 }
 
 template <typename K> static void allow_lds(K kernel, size_t bytes) {
@@ -1040,10 +1066,9 @@ static void plane_inv(const xfft_problem *p, FftArgs A, int nrhs, hipStream_t s,
     if (!init) { allow_lds(k_fft_plane_inv<T, N>, lds); init = true; }
     k_fft_plane_inv<T, N><<<plane_grid(p, nrhs), PlaneCfg<N>::NT, lds, s>>>(A, tw, spec, mode, out, u, d, nrhs, E);
 }
-template <typename T, int N2>
-static void zpass(const xfft_problem *p, FftArgs A, int nrhs, hipStream_t s, const Tables<T> &tb, cpx<T> *spec,
-                  int64_t sz, int64_t sy, const EnrUpd<T> &E) {
-    constexpr int TK = tkz_t<T>(N2);
+template <typename T, int N2, int TK>
+static void zpass_tk(const xfft_problem *p, FftArgs A, int nrhs, hipStream_t s, const Tables<T> &tb, cpx<T> *spec,
+                     int64_t sz, int64_t sy, const EnrUpd<T> &E) {
     // LDS holds the 3 tk lines a workgroup uses (tk <= TK columns share the nh
     // columns evenly); at 128^3 in FP32 that is 13 of 16, which lets four
     // workgroups share a CU (64 registers, eight waves per SIMD)
@@ -1052,9 +1077,17 @@ static void zpass(const xfft_problem *p, FftArgs A, int nrhs, hipStream_t s, con
     const size_t lds = (size_t)3 * tk * line;
     static bool init = false;
     if (!init) { allow_lds(k_fft_z_t<T, N2, TK>, (size_t)3 * TK * line); init = true; }
-    const int64_t grid = ((int64_t)green_blocks<T>(p->g) + E.nblk) * nrhs;
+    const int64_t grid = ((int64_t)p->g.n1 * ntiles + E.nblk) * nrhs;
     k_fft_z_t<T, N2, TK><<<(unsigned)grid, 512, lds, s>>>(A, tb.tws[2], tb.half[0], tb.half[1], tb.half[2], spec,
                                                         sz, sy, nrhs, E);
+}
+template <typename T, int N2>
+static void zpass(const xfft_problem *p, FftArgs A, int nrhs, hipStream_t s, const Tables<T> &tb, cpx<T> *spec,
+                  int64_t sz, int64_t sy, const EnrUpd<T> &E) {
+    if (p->fft_ztile[sizeof(T) == 8 ? 1 : 0])
+        zpass_tk<T, N2, tkz_alt<T>(N2)>(p, A, nrhs, s, tb, spec, sz, sy, E);
+    else
+        zpass_tk<T, N2, tkz_t<T>(N2)>(p, A, nrhs, s, tb, spec, sz, sy, E);
 }
 
 // compile-time x and y passes (ztmpl sizes); return false when n has no such variant
@@ -1134,7 +1167,7 @@ void launch_green_forward(xfft_problem *p, Work<T> &w, const Tables<T> &tb, T *f
     EnrUpd<T> E = enr_update_args<T>(p, w, enr_mode, enr_out);
     if (g.nX == 0) E.nblk = 0;
     FftArgs A = fft_args<T>(p, flags, parity);
-    const bool plane = plane_path<T>(g);
+    const bool plane = use_plane<T>(p);
     int64_t sz, sy;
     if (plane) {
         sz = g.nh;
@@ -1174,7 +1207,7 @@ void launch_green_forward(xfft_problem *p, Work<T> &w, const Tables<T> &tb, T *f
     }
     {
         A.slot0 = p->slots.grn0;
-        dim3 grid((unsigned)green_blocks<T>(g) * nrhs, 1);
+        dim3 grid((unsigned)green_blocks<T>(p) * nrhs, 1);
         xfft_prof_mark(p, -1, s);
         if (ztmpl_size(g.n2)) {
             switch (g.n2) {
@@ -1214,7 +1247,7 @@ void launch_green_inverse(xfft_problem *p, Work<T> &w, const Tables<T> &tb, int 
     FftArgs A = fft_args<T>(p, flags, parity);
     EnrFin<T> E = enr_final_args<T>(p, w, g.nX ? enr_mode : 0);
     xfft_prof_mark(p, -1, s);
-    if (plane_path<T>(g)) {
+    if (use_plane<T>(p)) {
         switch (g.n0) {
             case 16: plane_inv<T, 16>(p, A, nrhs, s, tb.tws[0], w.spec, mode, out, w.u, w.d, E); break;
             case 32: plane_inv<T, 32>(p, A, nrhs, s, tb.tws[0], w.spec, mode, out, w.u, w.d, E); break;

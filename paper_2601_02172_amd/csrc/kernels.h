@@ -11,7 +11,11 @@ void set_depth(SlotLayout &L, const Geometry &g, int kz);
 int green_slots(const Geometry &g);
 // false when a line FFT of the grid would exceed what the generic passes handle
 bool fft_sizes_ok(int n0, int n1, int n2);
-template <typename T> int green_blocks(const Geometry &g);
+// z-pass workgroups per right-hand side in the problem's FFT variant
+template <typename T> int green_blocks(const xfft_problem *p);
+// the FFT variants a grid has in precision T: bit 0 set when the xy-plane
+// kernels and separate passes both exist, bit 1 when the z pass has two tiles
+template <typename T> int fft_variants(const Geometry &g);
 
 // Operator r(x) = A x + (macro-strain term) on up to nrhs right-hand sides.
 // x/xe may be null (zero input).  sign multiplies the outputs.  When flags is

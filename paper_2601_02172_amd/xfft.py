@@ -45,6 +45,7 @@ class Options(ctypes.Structure):
         ("discretization", ctypes.c_int32),
         ("voxel_matrices", ctypes.c_int32),
         ("warm_start", ctypes.c_int32),
+        ("fft_variant", ctypes.c_int32),
     ]
 
 
@@ -60,6 +61,7 @@ class Stats(ctypes.Structure):
         ("n_cut_elements", ctypes.c_int64),
         ("n_multilabel", ctypes.c_int64),
         ("voxel_matrices", ctypes.c_int32),
+        ("fft_variant", ctypes.c_int32),
     ]
 
 
@@ -159,7 +161,7 @@ class Problem:
     def __init__(self, n, length, levelset, phase, lame, *, rtol=1e-10, maxit=20000, precision="fp64",
                  snap_eps=1e-6, d0_scale=1.0, inner_rtol=1e-6, batch=True, device=0, check_every=8,
                  use_graph=True, autotune=True, stream=None, scheme="lcg", discretization="xfem",
-                 voxel_matrices="auto", warm_start=False):
+                 voxel_matrices="auto", warm_start=False, fft_variant="auto"):
         lib = _lib()
         self._h = None
         n = np.ascontiguousarray(n, dtype=np.int32)
@@ -182,6 +184,7 @@ class Problem:
         o.discretization = {"xfem": 0, "p1": 1}[discretization]
         o.voxel_matrices = {"auto": -1, "never": 0, "always": 1}[voxel_matrices]
         o.warm_start = int(bool(warm_start))
+        o.fft_variant = -1 if fft_variant == "auto" else int(fft_variant)
         h = ctypes.c_void_p()
         _check(lib.xfft_setup(_ip(n), _dp(length), _dp(L), _ip(ph), self.nphase, _dp(lame), ctypes.byref(o),
                               ctypes.byref(h)), "xfft_setup")
@@ -232,7 +235,7 @@ class Problem:
                    seconds_setup=st.seconds_setup, seconds_solve=st.seconds_solve,
                    n_enriched=st.n_enriched, n_irregular_voxels=st.n_irregular_voxels,
                    n_cut_elements=st.n_cut_elements, n_multilabel=st.n_multilabel,
-                   voxel_matrices=bool(st.voxel_matrices))
+                   voxel_matrices=bool(st.voxel_matrices), fft_variant=int(st.fft_variant))
         if disp:
             out["disp"] = d
         if stress:

@@ -193,6 +193,8 @@ int main(void) {
         BAD_OPT(voxel_matrices, -2);
         BAD_OPT(warm_start, 2);
         BAD_OPT(warm_start, -1);
+        BAD_OPT(fft_variant, 4);
+        BAD_OPT(fft_variant, -2);
         xfft_default_options(&o);
         o.scheme = XFFT_NLCG;
         o.precision = XFFT_MIXED;
@@ -205,6 +207,9 @@ int main(void) {
         xfft_default_options(&o);
         o.warm_start = 1;
         expect_valid(&c, &o, "warm start");
+        xfft_default_options(&o);
+        o.fft_variant = 3;
+        expect_valid(&c, &o, "fixed FFT variant");
 #undef BAD_OPT
     }
 
