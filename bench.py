@@ -44,6 +44,8 @@ REGULAR_OPS_PER_VOXEL = 36 + 6 * 12 + 18 + 48 + 24 + 3
 # copy-like calibration kernel for the HBM byte counters: elementwise negation of
 # a float32 buffer reads and writes exactly COPY_BYTES each
 COPY_BYTES = 256 << 20
+# the end-of-window marker: a negation of this many floats after the timed steps
+MARK_ELEMS = 1 << 16
 # kernel classes -> substrings of the HIP kernel names
 KERNEL_NAMES = {
     "regular_voxels": [r"k_regular<"],
@@ -62,9 +64,13 @@ def log(msg):
 
 
 def algorithmic_bytes(g, s, nrhs):
-    """Algorithmic HBM bytes per launch of each kernel class (one CG iteration).
+    """Algorithmic HBM bytes per launch of each kernel class (one CG iteration)
+    processing nrhs loads (may be fractional: the mean over launches).
 
-    g: dict with N, nX, nirr, n0, n1, n2; s: bytes per real (4 or 8).
+    g: dict with N, nX, nirr, n0, n1, n2; s: bytes per real (4 or 8).  The
+    regular-voxel operator moves 2F per load (read d, write z) plus one byte of
+    material per voxel once per launch, and the launch also carries the
+    enriched gather.
     """
     N, nX, nirr = g["N"], g["nX"], g["n_irregular_voxels"]
     nh = g["n0"] // 2 + 1
@@ -73,8 +79,8 @@ def algorithmic_bytes(g, s, nrhs):
     field = 3 * N * s                            # one 3-component nodal field
     gather = nX * (8 * 4 + 3 * s)                # enriched gather: source ids, write z~
     per = {
-        # read d, write z, read material ids; the launch also runs the enriched gather
-        "regular_voxels": 2 * field + 4 * N + gather,
+        # read d, write z; the launch also runs the enriched gather (material: below)
+        "regular_voxels": 2 * field + gather,
         # u, level set, enriched ids, labels, scaled enriched d, corner forces; moments per cut element
         "irregular_voxels": nirr * (8 * 3 * s + 8 * s + 8 * 4 + 12 * 4 + 8 * 3 * s + 48 * s)
                             + g.get("n_cut_elements", 0) * 12 * s,
@@ -88,7 +94,9 @@ def algorithmic_bytes(g, s, nrhs):
         "enriched_update": nX * 3 * s * 5,
         "scalars": 0,
     }
-    return {k: v * nrhs for k, v in per.items()}
+    out = {k: v * nrhs for k, v in per.items()}
+    out["regular_voxels"] += N                   # one byte of material per voxel, once per launch
+    return out
 
 
 def source_digest():
@@ -118,7 +126,8 @@ def _kernel_class(name):
 def pmc_summary(fetch_csv, write_csv):
     """Mean HBM bytes per dispatch of every kernel class from two rocprofv3 --pmc runs
     (FETCH_SIZE, then WRITE_SIZE, both in KiB), scaled by the counter readings of the
-    calibration copy (reads and writes COPY_BYTES)."""
+    calibration copy (reads and writes COPY_BYTES).  Only the dispatches of the timed
+    steps count: those between the calibration copy and the end marker."""
     import csv
     per = {}
     for path, counter in ((fetch_csv, "FETCH_SIZE"), (write_csv, "WRITE_SIZE")):
@@ -127,14 +136,17 @@ def pmc_summary(fetch_csv, write_csv):
             for row in csv.DictReader(f):
                 if row["Counter_Name"] != counter:
                     continue
-                key = row["Dispatch_Id"]
+                key = int(row["Dispatch_Id"])
                 rows.setdefault(key, [row["Kernel_Name"], 0.0])[1] += float(row["Counter_Value"]) * 1024.0
-        copy = [v for n, v in rows.values() if "neg_kernel" in n]
-        if not copy:
-            raise SystemExit(f"no calibration copy dispatch in {path}")
-        factor = COPY_BYTES / max(copy)
+        negs = sorted(k for k, (n, v) in rows.items() if "neg_kernel" in n)
+        if len(negs) < 2:
+            raise SystemExit(f"no calibration copy and end marker in {path}")
+        first, last = negs[0], negs[-1]
+        factor = COPY_BYTES / rows[first][1]
         per[counter] = factor
-        for n, v in rows.values():
+        for k, (n, v) in rows.items():
+            if not first < k < last:
+                continue
             kc = _kernel_class(n)
             if kc is None:
                 continue
@@ -169,8 +181,25 @@ def load_traffic(workload):
     return data
 
 
-def cpu_baseline(cfg, fp64_iters, sample_cut=2000, sample_iters=2):
-    """Time the CPU oracle on a bounded sample of the workload and scale to solves/s."""
+def cpu_model():
+    """Model name of the host CPU (first 'model name' line of /proc/cpuinfo)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline(cfg, fp64_iters, sample_cut=8000, sample_iters=2):
+    """Time the CPU oracle on a bounded sample of the workload and scale to solves/s.
+
+    The oracle runs single-threaded (BLAS and FFT thread pools limited to one
+    thread); ``cores`` is that thread count, and the host's CPU model and
+    logical CPU count are reported beside it."""
     from threadpoolctl import threadpool_limits
     from oracle.xfem import Discretization
     from oracle.system import System
@@ -191,6 +220,7 @@ def cpu_baseline(cfg, fp64_iters, sample_cut=2000, sample_iters=2):
         t_iter = (time.perf_counter() - t0) / sample_iters
     total = t_setup + float(np.sum(fp64_iters)) * t_iter
     return dict(value=6.0 / total, unit="solves/s", cores=1, kind="oracle",
+                cpu_model=cpu_model(), host_logical_cpus=os.cpu_count(),
                 sample=(f"oracle setup with {min(sample_cut, ncut)} of {ncut} cut elements built "
                         f"(scaled to all), {sample_iters} PCG iterations of one load at full size; "
                         f"scaled to 6 loads x the FP64 path's iteration counts ({int(np.sum(fp64_iters))} total); "
@@ -309,20 +339,23 @@ def main():
     lay.update(n0=cfg["n"][0], n1=cfg["n"][1], n2=cfg["n"][2])
     log(f"setup {setup_s:.3f}s, nX={lay['nX']}, irregular voxels={lay['n_irregular_voxels']}")
 
-    # calibration copy for the byte counters (outside the timed region)
-    src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
-    dst = torch.neg(src)
-    torch.cuda.synchronize()
-    del src, dst
-
     for _ in range(args.warmup):
         pm.solve(E, c_eff=True)
     torch.cuda.synchronize()
+    # calibration copy for the byte counters, right before the timed steps; a
+    # small negation after them marks the end of the counted window
+    src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
+    dst = torch.neg(src)
+    mark = torch.ones(MARK_ELEMS, dtype=torch.float32, device="cuda")
+    torch.cuda.synchronize()
+    del src, dst
     t0 = time.perf_counter()
     for _ in range(args.steps):
         r_mixed = pm.solve(E, c_eff=True)
     torch.cuda.synchronize()
     t_mixed = time.perf_counter() - t0
+    torch.neg(mark)
+    torch.cuda.synchronize()
     # the same steps again with a HIP event before and after every kernel launch
     # (launched one by one instead of by graph replay; kernel durations are the same)
     pm.profile_begin()
@@ -397,28 +430,29 @@ def main():
         active = min(6.0, float(np.sum(r_mixed["iters"])) * args.steps / max(dom_n, 1))
     else:
         active = 6.0
-    bytes_launch = byts[dom_prec][dom] * active / 6.0
+    bytes_launch = algorithmic_bytes(lay, 4 if dom_prec == "fp32" else 8, active)[dom]
     achieved = bytes_launch / (dom_ms * 1e-3) / 1e9 if dom_ms > 0 else 0.0
     traffic = None
     tr = load_traffic(args.workload)
     if tr is not None and f"{dom}/{dom_prec}" in tr["kernels"]:
         traffic = tr["kernels"][f"{dom}/{dom_prec}"]["bytes_per_launch"]
-    # the binding roof: the larger of the ideal memory time and the ideal VALU time
+    # The path streams nodal fields (no dense contraction), so the roof reported is
+    # HBM bandwidth: algorithmic bytes per launch over the launch time against
+    # 8 TB/s.  For the regular-voxel operator, whose arithmetic per voxel is fixed
+    # by the edge form, the VALU issue fraction is reported beside it.
     ops_launch = REGULAR_OPS_PER_VOXEL * lay["N"] * active if dom == "regular_voxels" else None
-    t_hbm = bytes_launch / (HBM_PEAK_GBS * 1e9)
-    t_alu = ops_launch / (VALU_PEAK_TOPS * 1e12) if ops_launch else 0.0
-    common = dict(kernel=f"{dom} ({dom_prec})", traffic=traffic, bytes_per_launch=int(bytes_launch),
-                  ms_per_launch=round(dom_ms, 5), launches=dom_n, mean_active_loads=round(active, 3),
-                  traffic_over_algorithmic=round(traffic / bytes_launch, 3) if traffic else None,
-                  hbm_gbs=round(achieved, 1), hbm_frac=round(achieved / HBM_PEAK_GBS, 4))
-    if t_alu > t_hbm:
+    valu = None
+    if ops_launch:
         tops = ops_launch / (dom_ms * 1e-3) / 1e12
-        roofline = dict(bound="alu", achieved=round(tops, 3), peak=round(VALU_PEAK_TOPS, 2),
-                        unit="Tops/s (VALU lane operations, no packed FP32)", frac=round(tops / VALU_PEAK_TOPS, 4),
-                        ops_per_launch=int(ops_launch), **common)
-    else:
-        roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                        frac=round(achieved / HBM_PEAK_GBS, 4), **common)
+        valu = dict(achieved=round(tops, 3), peak=round(VALU_PEAK_TOPS, 2),
+                    unit="Tops/s (VALU lane operations, no packed FP32)", frac=round(tops / VALU_PEAK_TOPS, 4),
+                    ops_per_launch=int(ops_launch), ops_per_voxel=REGULAR_OPS_PER_VOXEL)
+    roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
+                    kernel=f"{dom} ({dom_prec})", bytes_per_launch=int(bytes_launch),
+                    ms_per_launch=round(dom_ms, 5), launches=dom_n, mean_active_loads=round(active, 3),
+                    traffic_over_algorithmic=round(traffic / bytes_launch, 3) if traffic else None,
+                    valu=valu)
     # per-kernel breakdown of one CG iteration with all six loads active
     prof = pm.profile(precision="fp32", nrhs=6, nrep=10)
     kernels = {k: dict(ms=round(v[0], 5), launches_per_iter=v[1] / 10.0,
