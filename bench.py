@@ -12,6 +12,8 @@ the stopping criterion:
 
 Both C_eff are compared with a reference (the oracle's C_eff when its stored
 value exists, else an FP64 GPU solve at 1e-13) and their errors are printed.
+For the comparison at equal C_eff error, both paths are also run at the
+tolerances 1e-8 ... 1e-12 (one timed step each, ``rtol_sweep``).
 Setup (level-set classification, enriched numbering, D0, FFT tables) is timed
 separately and is not part of a step.
 
@@ -294,6 +296,8 @@ def main():
     ap.add_argument("--inner-rtol", type=float, default=1e-6)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-sweep", action="store_true",
+                    help="skip the tolerance sweep (C_eff error and time of both paths at rtol 1e-8 ... 1e-12)")
     ap.add_argument("--schemes", action="store_true",
                     help="also time the FP64 solution schemes (linear CG, nonlinear CG, Barzilai-Borwein, basic), "
                          "6 loads batched, one step each")
@@ -416,6 +420,28 @@ def main():
     if schemes:
         for v in schemes.values():
             v["c_eff_rel_error"] = float(np.linalg.norm(v.pop("c_eff") - C_ref) / nrm)
+    # equal-error comparison: both paths over a range of tolerances, one timed
+    # step each after one untimed solve (autotuning, graph capture)
+    sweep = None
+    if not args.no_sweep and fp64 and args.workload == "spheres128":
+        sweep = []
+        for rt in (1e-8, 1e-9, 1e-10, 1e-11, 1e-12):
+            row = {"rtol": rt}
+            for name, prec, batch in (("mixed", "mixed", True), ("fp64", "fp64", False)):
+                q = Problem(cfg["n"], cfg["length"], cfg["L"], cfg["phase"], cfg["lame"], rtol=rt,
+                            precision=prec, batch=batch, inner_rtol=args.inner_rtol)
+                q.solve(E, c_eff=True)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                rq = q.solve(E, c_eff=True)
+                torch.cuda.synchronize()
+                tq = time.perf_counter() - t0
+                q.close()
+                row[name] = dict(ms_per_step=round(1000.0 * tq, 3), solves_per_s=round(6.0 / tq, 3),
+                                 c_eff_rel_error=float(np.linalg.norm(rq["c_eff"] - C_ref) / nrm))
+            log(f"rtol {rt:g}: mixed {row['mixed']['ms_per_step']} ms err {row['mixed']['c_eff_rel_error']:.2e}; "
+                f"fp64 {row['fp64']['ms_per_step']} ms err {row['fp64']['c_eff_rel_error']:.2e}")
+            sweep.append(row)
     # dominant kernel of the timed region: largest total time among all launches
     byts = {"fp32": algorithmic_bytes(lay, 4, 6), "fp64": algorithmic_bytes(lay, 8, 6)}
     totals = {k: m * c for k, (m, c) in region.items()}
@@ -511,6 +537,7 @@ def main():
         "timed_region_kernels": region_summary,
         "loss_gradient": grad_info,
         "schemes": schemes,
+        "rtol_sweep": sweep,
     }
     print(json.dumps(out))
 
