@@ -58,7 +58,8 @@ template <typename T> int alloc_work(xfft_problem *p, Work<T> &w, int cap) {
     free_work(w);
     const Geometry &g = p->g;
     const size_t nf = (size_t)cap * 3 * g.N, ne = (size_t)cap * 3 * (g.nX > 0 ? g.nX : 1);
-    const size_t ns = (size_t)cap * 3 * g.n2 * g.n1 * g.nh;
+    // half spectrum in the larger (padded) of its two layouts
+    const size_t ns = (size_t)cap * 3 * g.n2 * g.n1 * spec_row_stride(g.nh);
     const size_t nc = (size_t)cap * (size_t)cut_rows(g.nirr > 0 ? g.nirr : 1) * 48;
     T **fe_ptrs[] = {&w.u, &w.f, &w.d, &w.z};
     for (T **q : fe_ptrs)
@@ -286,25 +287,37 @@ int autotune_fft(xfft_problem *p, Work<T> &w, const Tables<T> &tb, int nrhs) {
         hipEvent_t e0, e1;
         HIP_OK(hipEventCreate(&e0));
         HIP_OK(hipEventCreate(&e1));
-        float best_ms = 1e30f;
-        for (int v = 0; v < 4; ++v) {
-            if ((v & ~have) != 0) continue;
-            p->fft_plane[pi] = (v & 1) ? 0 : 1;
-            p->fft_ztile[pi] = (v >> 1) & 1;
-            launch_green_forward<T>(p, w, tb, w.f, nullptr, nrhs, nullptr, 0, s, 0, nullptr);
-            launch_green_inverse<T>(p, w, tb, 2, nullptr, nrhs, nullptr, 0, s, 2);
-            (void)hipEventRecord(e0, s);
-            for (int rep = 0; rep < 5; ++rep) {
+        // two interleaved rounds over the variants, the faster of each variant's
+        // two timings counts; another variant replaces the default only when it
+        // is at least 3 % faster (timings of close variants scatter by a few %)
+        float t[4] = {1e30f, 1e30f, 1e30f, 1e30f};
+        bool ok = true;
+        for (int round = 0; round < 2 && ok; ++round) {
+            for (int v = 0; v < 4 && ok; ++v) {
+                if ((v & ~have) != 0) continue;
+                p->fft_plane[pi] = (v & 1) ? 0 : 1;
+                p->fft_ztile[pi] = (v >> 1) & 1;
                 launch_green_forward<T>(p, w, tb, w.f, nullptr, nrhs, nullptr, 0, s, 0, nullptr);
                 launch_green_inverse<T>(p, w, tb, 2, nullptr, nrhs, nullptr, 0, s, 2);
+                (void)hipEventRecord(e0, s);
+                for (int rep = 0; rep < 5; ++rep) {
+                    launch_green_forward<T>(p, w, tb, w.f, nullptr, nrhs, nullptr, 0, s, 0, nullptr);
+                    launch_green_inverse<T>(p, w, tb, 2, nullptr, nrhs, nullptr, 0, s, 2);
+                }
+                (void)hipEventRecord(e1, s);
+                float ms = 0.0f;
+                if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+                    ok = false;
+                    break;
+                }
+                if (ms < t[v]) t[v] = ms;
             }
-            (void)hipEventRecord(e1, s);
-            float ms = 0.0f;
-            if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) break;
-            if (ms < best_ms) { best_ms = ms; best = v; }
         }
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
+        float best_ms = t[0];
+        for (int v = 1; v < 4; ++v)
+            if (t[v] < 0.97f * t[0] && t[v] < best_ms) { best_ms = t[v]; best = v; }
         if (hipGetLastError() != hipSuccess) return XFFT_EDEVICE;
         cache[key] = best;
     }

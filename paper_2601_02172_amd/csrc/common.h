@@ -97,6 +97,10 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double *red) {
 // ------------------------------------------------------------------ problem
 constexpr int NPART = 8;   // doubles per partial-sum slot: [0] dot, [1..6] stress integral
 
+// Row stride of the half spectrum in the layout of the separate x, y and z
+// passes: nh = n0 / 2 + 1 rounded up to a multiple of 8 values.
+inline int spec_row_stride(int nh) { return (nh + 7) & ~7; }
+
 struct Geometry {
     int n0, n1, n2, nh;     // nh = n0 / 2 + 1
     int64_t N;              // nodes = voxels

@@ -121,6 +121,7 @@ __device__ void lds_fft(cpx<T> *buf, int nlines, int lstride, const FftPlan &pl,
 
 struct FftArgs {
     int n0, n1, n2, nh;
+    int nhs;                 // row stride of the spectrum (>= nh; padded in the [c][kz][ky][kx] layout)
     int64_t N, specN;        // nodes; complex entries per component spectrum... per rhs: 3 * specN
     const Flags *flags;
     int parity;
@@ -141,7 +142,7 @@ __global__ __launch_bounds__(256) void k_fft_x_fwd(FftArgs A, FftPlan pl, const 
     cpx<T> *sh = reinterpret_cast<cpx<T> *>(smem_raw);
     const int r = blockIdx.y;
     if (!active_rhs(A, r)) return;
-    const int n0 = A.n0, nh = A.nh;
+    const int n0 = A.n0, nh = A.nh, nhs = A.nhs;
     const int lstride = n0 + 1;
     const int64_t npairs = (int64_t)3 * A.n2 * A.n1 / 2;
     const T alpha = z ? (T)A.scal[r].alpha : (T)0;
@@ -176,9 +177,17 @@ __global__ __launch_bounds__(256) void k_fft_x_fwd(FftArgs A, FftPlan pl, const 
             const cpx<T> Zm = sh[lp * lstride + (kx == 0 ? 0 : n0 - kx)];
             const cpx<T> Av = {(T)0.5 * (Zk.x + Zm.x), (T)0.5 * (Zk.y - Zm.y)};
             const cpx<T> Bv = {(T)0.5 * (Zk.y + Zm.y), (T)-0.5 * (Zk.x - Zm.x)};
-            sr[(2 * pr) * nh + kx] = Av;
-            sr[(2 * pr + 1) * nh + kx] = Bv;
+            sr[(2 * pr) * nhs + kx] = Av;
+            sr[(2 * pr + 1) * nhs + kx] = Bv;
         }
+    }
+    // zeros in the row padding: the rows of the workgroup are written as one
+    // contiguous stream of whole cache lines
+    const int pad = nhs - nh;
+    for (int idx = threadIdx.x; idx < pairs_per_block * 2 * pad; idx += blockDim.x) {
+        const int lr = idx / pad, k = idx - lr * pad;
+        const int64_t row = 2 * p0 + lr;
+        if (row < 2 * npairs) sr[row * nhs + nh + k] = cpx<T>{0, 0};
     }
 }
 
@@ -189,24 +198,24 @@ __global__ __launch_bounds__(256) void k_fft_y(FftArgs A, FftPlan pl, const cpx<
     cpx<T> *sh = reinterpret_cast<cpx<T> *>(smem_raw);
     const int r = blockIdx.y;
     if (!active_rhs(A, r)) return;
-    const int n1 = A.n1, nh = A.nh;
+    const int n1 = A.n1, nh = A.nh, nhs = A.nhs;
     const int lstride = n1 + 1;
     const int ntiles = (nh + tk - 1) / tk;
     const int tile = blockIdx.x % ntiles;
     const int plane = blockIdx.x / ntiles;          // c * n2 + k
     const int kx0 = tile * tk;
-    cpx<T> *base = spec + (int64_t)r * 3 * A.specN + (int64_t)plane * n1 * nh;
+    cpx<T> *base = spec + (int64_t)r * 3 * A.specN + (int64_t)plane * n1 * nhs;
     for (int idx = threadIdx.x; idx < tk * n1; idx += blockDim.x) {
         const int kl = idx % tk, yy = idx / tk;
         const int kx = kx0 + kl;
-        sh[kl * lstride + yy] = (kx < nh) ? base[(int64_t)yy * nh + kx] : cpx<T>{0, 0};
+        sh[kl * lstride + yy] = (kx < nh) ? base[(int64_t)yy * nhs + kx] : cpx<T>{0, 0};
     }
     __syncthreads();
     lds_fft<T, INV>(sh, tk, lstride, pl, tw);
     for (int idx = threadIdx.x; idx < tk * n1; idx += blockDim.x) {
         const int kl = idx % tk, yy = idx / tk;
         const int kx = kx0 + kl;
-        if (kx < nh) base[(int64_t)yy * nh + kx] = sh[kl * lstride + yy];
+        if (kx < nh) base[(int64_t)yy * nhs + kx] = sh[kl * lstride + yy];
     }
 }
 
@@ -319,7 +328,7 @@ __global__ __launch_bounds__(256) void k_fft_x_inv(FftArgs A, FftPlan pl, const 
     cpx<T> *sh = reinterpret_cast<cpx<T> *>(smem_raw);
     const int r = blockIdx.y;
     if (!active_rhs(A, r)) return;
-    const int n0 = A.n0, nh = A.nh;
+    const int n0 = A.n0, nh = A.nh, nhs = A.nhs;
     const int lstride = n0 + 1;
     const int64_t npairs = (int64_t)3 * A.n2 * A.n1 / 2;
     const cpx<T> *sr = spec + (int64_t)r * 3 * A.specN;
@@ -331,7 +340,7 @@ __global__ __launch_bounds__(256) void k_fft_x_inv(FftArgs A, FftPlan pl, const 
         if (pr < npairs) {
             const bool lo = k < nh;
             const int kk = lo ? k : n0 - k;
-            cpx<T> Av = sr[(2 * pr) * nh + kk], Bv = sr[(2 * pr + 1) * nh + kk];
+            cpx<T> Av = sr[(2 * pr) * nhs + kk], Bv = sr[(2 * pr + 1) * nhs + kk];
             if (!lo) { Av.y = -Av.y; Bv.y = -Bv.y; }
             Zv = {Av.x - Bv.y, Av.y + Bv.x};
         }
@@ -416,9 +425,17 @@ __global__ __launch_bounds__(256) void k_fft_x_fwd_t(FftArgs A, const cpx<T> *tw
         if (pr < npairs) {
             const cpx<T> Zk = sh[lp * C::LS + fft_pad(kx)];
             const cpx<T> Zm = sh[lp * C::LS + fft_pad(kx == 0 ? 0 : N - kx)];
-            sr[(2 * pr) * C::NH + kx] = {(T)0.5 * (Zk.x + Zm.x), (T)0.5 * (Zk.y - Zm.y)};
-            sr[(2 * pr + 1) * C::NH + kx] = {(T)0.5 * (Zk.y + Zm.y), (T)-0.5 * (Zk.x - Zm.x)};
+            sr[(2 * pr) * A.nhs + kx] = {(T)0.5 * (Zk.x + Zm.x), (T)0.5 * (Zk.y - Zm.y)};
+            sr[(2 * pr + 1) * A.nhs + kx] = {(T)0.5 * (Zk.y + Zm.y), (T)-0.5 * (Zk.x - Zm.x)};
         }
+    }
+    // zeros in the row padding: the rows of the workgroup are written as one
+    // contiguous stream of whole cache lines
+    const int pad = A.nhs - C::NH;
+    for (int idx = threadIdx.x; idx < C::PP * 2 * pad; idx += 256) {
+        const int lr = idx / pad, k = idx - lr * pad;
+        const int64_t row = 2 * p0 + lr;
+        if (row < 2 * npairs) sr[row * A.nhs + C::NH + k] = cpx<T>{0, 0};
     }
 }
 
@@ -443,7 +460,7 @@ __global__ __launch_bounds__(256) void k_fft_x_inv_t(FftArgs A, const cpx<T> *tw
         if (pr < npairs) {
             const bool lo = k < C::NH;
             const int kk = lo ? k : N - k;
-            cpx<T> Av = sr[(2 * pr) * C::NH + kk], Bv = sr[(2 * pr + 1) * C::NH + kk];
+            cpx<T> Av = sr[(2 * pr) * A.nhs + kk], Bv = sr[(2 * pr + 1) * A.nhs + kk];
             if (!lo) { Av.y = -Av.y; Bv.y = -Bv.y; }
             Zv = {Av.x - Bv.y, Av.y + Bv.x};
         }
@@ -493,16 +510,16 @@ __global__ __launch_bounds__(256) void k_fft_y_t(FftArgs A, const cpx<T> *tw, cp
     if (!active_rhs(A, r)) return;
     const int tile = blk % ntiles, plane = blk / ntiles;       // plane = c * n2 + kz
     const int kx0 = tile * tk, ncol = min(tk, nh - kx0);
-    cpx<T> *base = spec + (int64_t)r * 3 * A.specN + (int64_t)plane * N1 * nh + kx0;
+    cpx<T> *base = spec + (int64_t)r * 3 * A.specN + (int64_t)plane * N1 * A.nhs + kx0;
     for (int idx = threadIdx.x; idx < TK * N1; idx += 256) {
         const int kl = idx % TK, yy = idx / TK;
-        if (kl < tk) sh[kl * LS + fft_pad(yy)] = kl < ncol ? base[(int64_t)yy * nh + kl] : cpx<T>{0, 0};
+        if (kl < tk) sh[kl * LS + fft_pad(yy)] = kl < ncol ? base[(int64_t)yy * A.nhs + kl] : cpx<T>{0, 0};
     }
     __syncthreads();
     fft_lines<T, N1, TK, 256, INV>(sh, tw, tk);
     for (int idx = threadIdx.x; idx < TK * N1; idx += 256) {
         const int kl = idx % TK, yy = idx / TK;
-        if (kl < ncol) base[(int64_t)yy * nh + kl] = sh[kl * LS + fft_pad(yy)];
+        if (kl < ncol) base[(int64_t)yy * A.nhs + kl] = sh[kl * LS + fft_pad(yy)];
     }
 }
 
@@ -954,7 +971,7 @@ template <typename T> int tk_for(int n, int lines_factor, int threads) {
 template <typename T>
 FftArgs fft_args(xfft_problem *p, const Flags *flags, int parity) {
     FftArgs A;
-    A.n0 = p->g.n0; A.n1 = p->g.n1; A.n2 = p->g.n2; A.nh = p->g.nh;
+    A.n0 = p->g.n0; A.n1 = p->g.n1; A.n2 = p->g.n2; A.nh = p->g.nh; A.nhs = p->g.nh;
     A.N = p->g.N;
     A.specN = (int64_t)p->g.n2 * p->g.n1 * p->g.nh;
     A.flags = flags; A.parity = parity; A.scal = p->scal;
@@ -977,6 +994,14 @@ template <typename T> static bool plane_path(const Geometry &g) {
 // the xy-plane kernels run when the grid has them and the problem's variant selects them
 template <typename T> static bool use_plane(const xfft_problem *p) {
     return plane_path<T>(p->g) && p->fft_plane[sizeof(T) == 8 ? 1 : 0] != 0;
+}
+// Spectrum layout of a Green application: the xy-plane kernels keep rows of nh
+// values ([c][ky][kz][kx]); the separate passes ([c][kz][ky][kx]) pad the rows to
+// a multiple of 8 values, so that the kx runs the y and z passes move start on
+// 64-byte (FP32) or 128-byte (FP64) boundaries instead of straddling cache lines.
+template <typename T> static void set_spec_layout(const xfft_problem *p, FftArgs &A) {
+    A.nhs = use_plane<T>(p) ? p->g.nh : spec_row_stride(p->g.nh);
+    A.specN = (int64_t)p->g.n2 * p->g.n1 * A.nhs;
 }
 // kx columns per z-pass workgroup: 3 x TK lines of n2 complex values in LDS
 // (about 50 KB, three workgroups per CU)
@@ -1167,6 +1192,7 @@ void launch_green_forward(xfft_problem *p, Work<T> &w, const Tables<T> &tb, T *f
     EnrUpd<T> E = enr_update_args<T>(p, w, enr_mode, enr_out);
     if (g.nX == 0) E.nblk = 0;
     FftArgs A = fft_args<T>(p, flags, parity);
+    set_spec_layout<T>(p, A);
     const bool plane = use_plane<T>(p);
     int64_t sz, sy;
     if (plane) {
@@ -1183,8 +1209,8 @@ void launch_green_forward(xfft_problem *p, Work<T> &w, const Tables<T> &tb, T *f
         }
         xfft_prof_mark(p, K_FFT_X_FWD + (sizeof(T) == 8 ? K_COUNT : 0), s);
     } else {
-        sz = (int64_t)g.n1 * g.nh;
-        sy = g.nh;
+        sz = (int64_t)g.n1 * A.nhs;
+        sy = A.nhs;
         {
             const int pp = pairs_for<T>(g.n0);
             const int64_t npairs = (int64_t)3 * g.n2 * g.n1 / 2;
@@ -1245,6 +1271,7 @@ void launch_green_inverse(xfft_problem *p, Work<T> &w, const Tables<T> &tb, int 
                           const Flags *flags, int parity, hipStream_t s, int enr_mode) {
     const Geometry &g = p->g;
     FftArgs A = fft_args<T>(p, flags, parity);
+    set_spec_layout<T>(p, A);
     EnrFin<T> E = enr_final_args<T>(p, w, g.nX ? enr_mode : 0);
     xfft_prof_mark(p, -1, s);
     if (use_plane<T>(p)) {
