@@ -157,3 +157,20 @@ def test_iteration_count_matches_oracle_cube32(rotated):
         r = p.solve(eb)
     assert r["converged"]
     assert all(abs(int(a) - b) <= 1 for a, b in zip(r["iters"], it_or)), (r["iters"], it_or)
+
+
+@pytest.mark.parametrize("nphase", [384, 400])
+def test_operator_many_phases(nphase):
+    # many phases: a label drawn per node from nphase phases (every voxel mixes
+    # several materials, most elements differ from their neighbours), the
+    # operator against the oracle
+    from paper_2601_02172_amd import Problem
+    n = (16, 16, 16)
+    L, _ = ms.spheres_levelset(n, [np.array([7.7, 8.3, 8.1])], [4.6])
+    rng = np.random.default_rng(nphase)
+    ph = rng.integers(0, nphase, size=L.size).astype(np.int32)
+    lame = np.stack([rng.uniform(0.2, 3.0, nphase), rng.uniform(0.3, 2.0, nphase)], axis=1)
+    d = Discretization(n, tuple(float(v) for v in n), L, ph, lame, keep_qp=False)
+    with Problem(n, [float(v) for v in n], L, ph, lame) as p:
+        assert p.nX == d.nX
+        _check_operator(p, System(d), d, 11)
