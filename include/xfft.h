@@ -112,10 +112,10 @@ typedef struct {
                                0 never; 1 always (also for xfft_apply_operator).  Costs 11.8 KB (FP64) / 5.9 KB
                                (FP32) of device memory per irregular voxel; falls back to the moment form when the
                                allocation fails.  Rebuilt after xfft_set_lame. */
-    int32_t warm_start;     /* 1: a solve of the six unit Mandel loads starts the CG of each load from that load's
-                               solution of the previous unit-load solve of this problem (same geometry, possibly
-                               other moduli after xfft_set_lame) instead of u = 0; other solves, and the first
-                               one, start from 0.  The converged result does not depend on the start; the stopping
+    int32_t warm_start;     /* 1: a solve of the six unit Mandel loads (xfft_solve, xfft_solve_device) starts the
+                               CG of each load from that load's solution of the previous unit-load solve of this
+                               problem (same geometry, possibly other moduli after xfft_set_lame) instead of
+                               u = 0; other solves, the first one and xfft_batch_solve start from 0.  The converged result does not depend on the start; the stopping
                                test of eq. stoppingCriterion is the same.  Default 0. */
     int32_t fft_variant;    /* kernels of the Green operator (eq. GreenHermitian): -1 (default) timed at the first
                                solve of a precision, the fastest kept (with autotune on; else 0); or fixed: bit 0

@@ -10,6 +10,7 @@
 #include <array>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -225,16 +226,34 @@ int cg_loop(xfft_problem *p, Work<T> &w, const Tables<T> &tb, int nrhs, int crit
     return it;
 }
 
+// The autotuners' results are kept per (grid, precision, loads) for the
+// process; distinct problems may be solved from several threads at once, so
+// the caches are read and written under a lock (the timing runs outside it).
+using TuneKey = std::array<int, 5>;
+std::mutex g_tune_mu;
+
+bool tune_lookup(std::map<TuneKey, int> &cache, const TuneKey &key, int &value) {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    auto it = cache.find(key);
+    if (it == cache.end()) return false;
+    value = it->second;
+    return true;
+}
+
+void tune_store(std::map<TuneKey, int> &cache, const TuneKey &key, int value) {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    cache[key] = value;
+}
+
 // Choose the regular-voxel operator depth (planes per block) by timing the
-// candidates in the solve's launch configuration; results are cached per
-// (grid, precision, loads) for the process.
+// candidates in the solve's launch configuration.
 template <typename T>
 int autotune_depth(xfft_problem *p, Work<T> &w, const Tables<T> &tb, int nrhs) {
-    static std::map<std::array<int, 5>, int> cache;
-    const std::array<int, 5> key = {p->g.n0, p->g.n1, p->g.n2, (int)sizeof(T), nrhs};
-    auto it = cache.find(key);
-    if (it != cache.end()) {
-        set_depth(p->slots, p->g, it->second);
+    static std::map<TuneKey, int> cache;
+    const TuneKey key = {p->g.n0, p->g.n1, p->g.n2, (int)sizeof(T), nrhs};
+    int cached = 0;
+    if (tune_lookup(cache, key, cached)) {
+        set_depth(p->slots, p->g, cached);
         return XFFT_OK;
     }
     hipStream_t s = p->stream;
@@ -260,7 +279,7 @@ int autotune_depth(xfft_problem *p, Work<T> &w, const Tables<T> &tb, int nrhs) {
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     set_depth(p->slots, p->g, best);
-    cache[key] = best;
+    tune_store(cache, key, best);
     return XFFT_OK;
 }
 
@@ -272,13 +291,12 @@ template <typename T>
 int autotune_fft(xfft_problem *p, Work<T> &w, const Tables<T> &tb, int nrhs) {
     const int pi = sizeof(T) == 8 ? 1 : 0;
     if (p->fft_tuned[pi]) return XFFT_OK;
-    static std::map<std::array<int, 5>, int> cache;
-    const std::array<int, 5> key = {p->g.n0, p->g.n1, p->g.n2, (int)sizeof(T), nrhs};
+    static std::map<TuneKey, int> cache;
+    const TuneKey key = {p->g.n0, p->g.n1, p->g.n2, (int)sizeof(T), nrhs};
     const int have = fft_variants<T>(p->g);
     int best = 0;
-    auto it = cache.find(key);
-    if (it != cache.end()) {
-        best = it->second;
+    if (tune_lookup(cache, key, best)) {
+        // chosen before for this grid
     } else if (have) {
         hipStream_t s = p->stream;
         // zero input: the timed transforms read defined values
@@ -319,7 +337,7 @@ int autotune_fft(xfft_problem *p, Work<T> &w, const Tables<T> &tb, int nrhs) {
         for (int v = 1; v < 4; ++v)
             if (t[v] < 0.97f * t[0] && t[v] < best_ms) { best_ms = t[v]; best = v; }
         if (hipGetLastError() != hipSuccess) return XFFT_EDEVICE;
-        cache[key] = best;
+        tune_store(cache, key, best);
     }
     p->fft_plane[pi] = (best & 1) ? 0 : 1;
     p->fft_ztile[pi] = (best >> 1) & 1;
