@@ -108,8 +108,9 @@ typedef struct {
     int32_t voxel_matrices; /* cached voxel matrices of the irregular voxels (Sec. 3, caching strategy): the
                                scaled 48 x 48 matrix of each irregular voxel (FP64, and FP32 rounded once) replaces
                                the moment form in the CG iterations (up to 6 loads per launch), read once for all
-                               loads: -1 (default) the faster of the two, timed at the first solve per precision;
-                               0 never; 1 always (also for xfft_apply_operator).  Costs 11.8 KB (FP64) / 5.9 KB
+                               loads: -1 (default) the faster of the two, timed at the first solve per precision
+                               (only when the tables fit in a quarter of the free device memory, else the moment
+                               form); 0 never; 1 always (also for xfft_apply_operator).  Costs 11.8 KB (FP64) / 5.9 KB
                                (FP32) of device memory per irregular voxel; falls back to the moment form when the
                                allocation fails.  Rebuilt after xfft_set_lame. */
     int32_t warm_start;     /* 1: a solve of the six unit Mandel loads (xfft_solve, xfft_solve_device) starts the

@@ -376,6 +376,15 @@ int ensure_voxel_matrices(xfft_problem *p, Work<T> &w, const Tables<T> &tb, int 
         return XFFT_OK;
     }
     if (!have()) {
+        // the automatic choice only tries tables that fit in a quarter of the
+        // free device memory (with the FP64 table the FP32 one is rounded from)
+        size_t free_b = 0, total_b = 0;
+        const size_t need = (size_t)p->g.nirr * VM_STRIDE * (sizeof(double) + (pi == 0 ? sizeof(float) : 0));
+        if (hipMemGetInfo(&free_b, &total_b) != hipSuccess || need > free_b / 4) {
+            p->vm_on[pi] = false;
+            p->vm_tuned[pi] = true;
+            return XFFT_OK;
+        }
         const int r = build();
         if (r == XFFT_EDEVICE) return r;
         if (r) { p->vm_on[pi] = false; p->vm_tuned[pi] = true; return XFFT_OK; }
