@@ -212,22 +212,65 @@ def cpu_baseline(cfg, fp64_iters, sample_cut=8000, sample_iters=2):
                            sample_cut=sample_cut)
         ncut = len(d.cut_voxel)
         t_setup = d.timing["uncut"] + d.timing["cut"] * ncut / max(d.timing["cut_built"], 1)
+        # assembly of the system and the Green operator (part of the oracle's work)
+        t0 = time.perf_counter()
         s = System(d)
         g = GreenOperator(d.n)
         eb = np.eye(6)[0]
         b = s.rhs(eb)
+        t_sys = time.perf_counter() - t0
         t0 = time.perf_counter()
         pcg(s.apply, b, lambda f: g.apply(f, d.nX), lambda x: s.average_stress(x, eb), d.volume, 0.0,
             sample_iters)
         t_iter = (time.perf_counter() - t0) / sample_iters
-    total = t_setup + float(np.sum(fp64_iters)) * t_iter
+    total = t_setup + t_sys + float(np.sum(fp64_iters)) * t_iter
     return dict(value=6.0 / total, unit="solves/s", cores=1, kind="oracle",
                 cpu_model=cpu_model(), host_logical_cpus=os.cpu_count(),
                 sample=(f"oracle setup with {min(sample_cut, ncut)} of {ncut} cut elements built "
-                        f"(scaled to all), {sample_iters} PCG iterations of one load at full size; "
-                        f"scaled to 6 loads x the FP64 path's iteration counts ({int(np.sum(fp64_iters))} total); "
-                        f"1 thread"),
-                seconds_setup_est=t_setup, seconds_per_iteration=t_iter)
+                        f"(scaled to all), system assembly, {sample_iters} PCG iterations of one load at full "
+                        f"size; scaled to 6 loads x the FP64 path's iteration counts ({int(np.sum(fp64_iters))} "
+                        f"total); 1 thread"),
+                seconds_setup_est=t_setup, seconds_assembly=t_sys, seconds_per_iteration=t_iter)
+
+
+def extrapolation_check(rtol, sample_cut=40, sample_iters=2):
+    """The cpu_baseline extrapolation checked where the oracle also runs in full:
+    the 16^3 single-sphere cell, one load.  Returns the extrapolated and the
+    measured seconds (setup plus solve to rtol, one thread)."""
+    from threadpoolctl import threadpool_limits
+    import microstructure as ms
+    from oracle.xfem import Discretization
+    from oracle.system import System
+    from oracle.green import GreenOperator
+    from oracle.solver import pcg
+    cfg = ms.config_single_sphere()
+    eb = cfg["loads"][0]
+    with threadpool_limits(1):
+        # full run: setup with every cut element built, PCG to the tolerance
+        t0 = time.perf_counter()
+        d = Discretization(cfg["n"], cfg["length"], cfg["L"], cfg["phase"], cfg["lame"], keep_qp=False)
+        s = System(d)
+        g = GreenOperator(d.n)
+        b = s.rhs(eb)
+        _, info = pcg(s.apply, b, lambda f: g.apply(f, d.nX), lambda x: s.average_stress(x, eb), d.volume,
+                      rtol, 100000)
+        t_full = time.perf_counter() - t0
+        # the same extrapolation as the baseline: sampled setup, a few timed iterations
+        ds = Discretization(cfg["n"], cfg["length"], cfg["L"], cfg["phase"], cfg["lame"], keep_qp=False,
+                            sample_cut=sample_cut)
+        t_setup = ds.timing["uncut"] + ds.timing["cut"] * len(ds.cut_voxel) / max(ds.timing["cut_built"], 1)
+        t0 = time.perf_counter()
+        s2, g2 = System(ds), GreenOperator(ds.n)
+        b2 = s2.rhs(eb)
+        t_sys = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        pcg(s2.apply, b2, lambda f: g2.apply(f, ds.nX), lambda x: s2.average_stress(x, eb), ds.volume, 0.0,
+            sample_iters)
+        t_iter = (time.perf_counter() - t0) / sample_iters
+    t_est = t_setup + t_sys + int(info["iters"]) * t_iter
+    return dict(workload="single_sphere16, 1 load, rtol %g" % rtol, iters=int(info["iters"]),
+                seconds_measured=round(t_full, 3), seconds_extrapolated=round(t_est, 3),
+                ratio=round(t_est / t_full, 3))
 
 
 def bench_uneven(args):
@@ -507,7 +550,8 @@ def main():
     if not args.no_cpu_baseline and fp64 and args.workload == "spheres128":
         log("timing the CPU oracle on a bounded sample")
         cpu = cpu_baseline(cfg, fp64["iters"])
-        log(f"cpu baseline {cpu['value']:.3e} solves/s")
+        cpu["extrapolation_check"] = extrapolation_check(args.rtol)
+        log(f"cpu baseline {cpu['value']:.3e} solves/s; extrapolation check {cpu['extrapolation_check']}")
 
     out = {
         "metric": "PCG solves/sec (6 loads, 128^3) mixed vs FP64 plain at equal C_eff error",
